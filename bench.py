@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSR Stage-2 hot path on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+sample (Philox) -> classify (dominance, LABEL mode) -> evaluate the
+unclassified samples (batched BFS) -> gradient counts -> estimate.  Workload:
+the 119-node / 295-edge random geometric graph with 1e4 lower + 1e4 upper
+reference rows and N = 1e6 samples.  The metric is dominance tests per
+second, counting every (sample, reference row) pair once: N * (R_L + R_U)
+per step.
+
+Besides the step, the dominant kernel (classification) is timed in COUNT mode,
+where every (sample, row) test is evaluated in full, against the vector-ALU
+roofline, and the CPU oracle is timed on a bounded sample of the same
+workload.  Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz 32-bit vector ops per second.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU-oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", default="popcount", choices=["auto", "popcount", "mfma"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
+              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2604_17066_amd as R
+    import workloads as WL
+
+    form = {"auto": R.RSR_AUTO, "popcount": R.RSR_POPCOUNT, "mfma": R.RSR_MFMA}[args.form]
+    t0 = time.time()
+    cfg = WL.configs.graph2()
+    N, n, K = cfg["N"], cfg["n"], cfg["K"]
+    R_L, R_U = cfg["lower"].shape[0], cfg["upper"].shape[0]
+    log(f"workload built in {time.time() - t0:.1f}s: n={n} R_L={R_L} R_U={R_U} N={N}")
+
+    ctx = R.Context(0)
+    model = R.Model(ctx, cfg["p"])
+    refs = R.Refs(ctx, n, K, cfg["lower"], cfg["upper"])
+    system = R.System(ctx, cfg["graph"])
+    buf = R.Buffers(ctx, n, K, N)
+    lib = R.lib()
+    P = R.api._ptr
+    h = ctx.h
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+
+    def step(i=None):
+        ctx.check(lib.rsr_sample(h, model.h, cfg["seed"], 0, 0, N, P(buf.samples)))
+        if i is not None:
+            ev[i][0].record()
+        ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, R.RSR_LABEL, form, P(buf.flags),
+                                   None))
+        if i is not None:
+            ev[i][1].record()
+        ctx.check(lib.rsr_eval_unknown(h, system.h, P(buf.samples), N, P(buf.flags),
+                                       R.RSR_UNKNOWN_ONLY, P(buf.Y), P(buf.n_eval)))
+        ctx.check(lib.rsr_grad(h, model.h, P(buf.samples), P(buf.Y), N, P(buf.G), None))
+        return R.rsr_estimate(ctx, buf.flags, buf.Y, N)
+
+    for _ in range(args.warmup):
+        est = step()
+    log(f"warmup done: P={est['P']:.6f} p_u={est['p_u']:.3e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        est = step(i)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms_per_step = (t2 - t1) * 1e3 / args.steps
+    tests = N * (R_L + R_U)
+    value = tests / (ms_per_step * 1e-3)
+    label_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, label classify {label_ms:.3f} ms")
+
+    # Dominant kernel in COUNT mode (every test evaluated in full).
+    reps = max(3, min(args.steps, 10))
+    cev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+    ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, R.RSR_COUNT, form, P(buf.flags),
+                               None))
+    for i in range(reps):
+        cev[i][0].record()
+        ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, R.RSR_COUNT, form,
+                                   P(buf.flags), None))
+        cev[i][1].record()
+    torch.cuda.synchronize()
+    count_ms = float(np.mean([a.elapsed_time(b) for a, b in cev]))
+    W = model.words
+    ops = float(tests) * W          # one 32-bit AND-OR per packed word per test
+    achieved = ops / (count_ms * 1e-3)
+    log(f"COUNT classify {count_ms:.3f} ms -> {achieved / 1e12:.2f} TOP/s")
+    # Restore LABEL flags so the buffers hold a consistent pass.
+    step()
+    torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, R_L + R_U, args.cpu_seconds)
+
+    out = {
+        "metric": "dominance tests/s (samples x reference states), whole Stage-2 step",
+        "value": value,
+        "unit": "tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "graph2: seeded 119-node / 295-edge random geometric graph, s-t "
+                        "connectivity, p_fail ~ U[0.01,0.20], 1e4 lower + 1e4 upper reference "
+                        "rows, N = 1e6 Philox samples; step = sample + classify (LABEL) + "
+                        "evaluate unknowns + gradient + estimate",
+            "n": n, "K": K, "R_L": R_L, "R_U": R_U, "N": N, "form": args.form,
+            "P": est["P"], "p_u": est["p_u"], "se": est["se"],
+        },
+        "roofline": {
+            "kernel": "rsr_classify (COUNT mode, every test in full), same workload and launch",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_OPS,
+            "traffic": None,
+            "ops_per_test": W,
+            "kernel_ms": count_ms,
+        },
+        "label_classify": {
+            "kernel_ms": label_ms,
+            "nominal_tests_per_s": tests / (label_ms * 1e-3),
+            "multiple_of_exhaustive_roofline": (tests / (label_ms * 1e-3)) / (VALU_PEAK_OPS / W),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg, R_total, seconds):
+    """The oracle as it stands, on the first N_sub samples of the same workload
+    (same seed), timed over the whole hot path on the host cores."""
+    import oracle
+    cores = oracle.get_threads()
+    g = cfg["graph"]
+
+    def run(n_sub):
+        t = time.perf_counter()
+        x = oracle.sample(cfg["p"], cfg["seed"], 0, 0, n_sub)
+        fl, _, _ = oracle.classify(cfg["lower"], cfg["upper"], x, mode=0)
+        Y, _ = oracle.eval_unknown(g, x, fl)
+        oracle.estimate(oracle.counts(fl, Y))
+        oracle.grad(cfg["p"], x, Y)
+        return time.perf_counter() - t
+
+    pilot_n = 2000
+    pilot = run(pilot_n)
+    n_sub = int(min(cfg["N"], max(pilot_n, pilot_n * seconds / max(pilot, 1e-6))))
+    t = run(n_sub)
+    log(f"cpu oracle: {n_sub} samples in {t:.2f}s on {cores} threads")
+    return {"value": n_sub * R_total / t, "unit": "tests/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_sub} of the {cfg['N']} samples of the same workload, whole "
+                      f"hot path (sample, classify, evaluate, estimate, gradient), {t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * rsr.h - C ABI of the MI355X (gfx950) library for the Stage-2 hot path of the
+ * Reference-state System Reliability (RSR) method, Byun, Ryu & Song,
+ * arXiv 2604.17066.
+ *
+ * The hot path, for one target system level:
+ *   rsr_sample        draw Monte Carlo component-state samples (section 3.1)
+ *   rsr_classify      classify them against lower / upper reference states
+ *                     (section 3.3, Algorithm 1, eq. violation_matrix)
+ *   rsr_eval_unknown  evaluate the system function on unclassified samples
+ *                     (section 3.5, Stage 2)
+ *   rsr_estimate      reduce labels to probability estimates (section 3.3.1)
+ *   rsr_grad          score-function partials dP/dp[i][s]
+ * plus handles for the problem data (component-state probabilities,
+ * reference states, system function) and a batched plan that runs many
+ * (model, system) jobs in one captured HIP graph.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* are device pointers owned by the caller; every other
+ *   pointer is host memory owned by the caller and only read during the call
+ *   (handles copy what they need).
+ * - All device work is enqueued on the HIP stream given to rsr_ctx_create, in
+ *   call order.  Only rsr_estimate, rsr_plan_results and the *_create calls
+ *   synchronise with the host.
+ * - Every call returns an rsr_status.  Nothing throws or aborts across the
+ *   ABI.  On failure the context keeps a message (rsr_last_error).  Inputs are
+ *   validated before any launch; asynchronous device faults surface as
+ *   RSR_EHIP at the next synchronising call.
+ * - A context is not thread-safe; use one per host thread.
+ *
+ * State encoding (the layout of d_samples)
+ * ----------------------------------------
+ * n components with K ordered states 0..K-1 (the paper's N and M, section
+ * 2.1).  A state vector x is stored as K-1 thermometer planes t_j = [x >= j],
+ * j = 1..K-1, plane-major, each plane padded to whole 32-bit words:
+ *   PW = ceil(n / 32) words per plane, W = (K-1) * PW words per sample,
+ *   bit (i mod 32) of word (j-1)*PW + i/32  =  [x_i >= j],  pad bits are 0.
+ * Samples are stored word-major: word w of sample h is d_samples[w * N + h].
+ * Componentwise x <= r holds iff t(x) AND NOT t(r) is all zero, and x >= r
+ * iff t(r) AND NOT t(x) is all zero, which is the zero test of the paper's
+ * violation matrix (section 3.3.2) on a K-1 bit code per component instead
+ * of the paper's K-bit one-hot / down-set / up-set code.
+ */
+#ifndef RSR_H
+#define RSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSR_OK = 0,
+    RSR_EINVAL = 1,       /* an argument failed validation; nothing was launched */
+    RSR_ENOMEM = 2,       /* a device or pinned-host allocation failed */
+    RSR_EHIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
+    RSR_EUNSUPPORTED = 4  /* valid request outside this build's limits */
+} rsr_status;
+
+enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
+enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2 };  /* rsr_classify form */
+enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown which */
+enum { RSR_SYS_ST_CONNECTIVITY = 1 };                   /* rsr_system_desc kind */
+
+/* Limits of this build. */
+#define RSR_MAX_K 16
+#define RSR_MAX_BITS 4096   /* n * (K-1) */
+#define RSR_MAX_NODES 4096
+
+typedef struct rsr_ctx rsr_ctx;
+typedef struct rsr_model rsr_model;
+typedef struct rsr_refs rsr_refs;
+typedef struct rsr_system rsr_system;
+typedef struct rsr_plan rsr_plan;
+
+/* Estimates (section 3.3.1).  Counts: n_L = #{lower-classified}, n_U =
+ * #{upper-classified and not lower}, n_u = #{unclassified}, n_both = #{samples
+ * with both flags} (0 for valid reference sets), n_u_up = #{unclassified with
+ * Y = 1}, N = samples.  p_L, p_U, p_u = the three counts over N;
+ * P = (n_U + n_u_up) / N estimates P(S >= level); se = sqrt(P (1-P) / N);
+ * cov = sqrt((1-P) / (N P)), +inf at P = 0.  Every division is in fp64 in
+ * exactly this form, so results are reproducible bit for bit. */
+typedef struct {
+    uint64_t n_L, n_U, n_u, n_both, n_u_up, N;
+    double p_L, p_U, p_u, P, se, cov;
+} rsr_estimate_t;
+
+/* System function description (section 2.1): components are the undirected
+ * edges (edge_u[e], edge_v[e]) of a graph with n_nodes nodes; n_edges = n.
+ * Phi = 1 when sink is reachable from source over edges whose state is at
+ * least `level` (1 <= level <= K-1), else 0: single-OD connectivity for
+ * K = 2, and the level-`level` bottleneck system for K > 2. */
+typedef struct {
+    int32_t kind;       /* RSR_SYS_ST_CONNECTIVITY */
+    int32_t n_nodes;    /* 2..RSR_MAX_NODES */
+    int32_t n_edges;    /* = n, the number of components */
+    int32_t K;          /* states per component */
+    const int32_t* edge_u;  /* host [n_edges], node ids in [0, n_nodes) */
+    const int32_t* edge_v;  /* host [n_edges] */
+    int32_t source, sink;   /* distinct node ids */
+    int32_t level;
+} rsr_system_desc;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  EHIP if the device is absent. */
+rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out);
+rsr_status rsr_ctx_destroy(rsr_ctx* ctx);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next
+ * call on ctx. */
+const char* rsr_last_error(const rsr_ctx* ctx);
+const char* rsr_status_str(rsr_status s);
+
+/* Words per sample, W = (K-1) * ceil(n/32); 0 for invalid n or K. */
+size_t rsr_words(int32_t n, int32_t K);
+
+/* Host helper, no device: inverse-CDF thresholds of a model (section 3.1).
+ * p is host [n][K] with rows of probabilities; C is host [n][K-1] with
+ * C[i][s-1] = min(floor(2^32 * (p[i][0] + ... + p[i][s-1])), 2^32), the sum
+ * formed left to right in fp64.  A sample's component i is in state
+ * #{s : u >= C[i][s-1]} for its 32-bit uniform word u.  EINVAL on a
+ * non-finite entry, an entry outside [0,1] or a row sum off 1 by > 1e-9. */
+rsr_status rsr_thresholds(int32_t n, int32_t K, const double* p, uint64_t* C);
+
+/* ---- problem data handles ---------------------------------------------- */
+
+/* Model: n independent components with state probabilities p (host [n][K],
+ * row i = P(X_i = 0..K-1); section 2.1).  Validates p as rsr_thresholds does,
+ * then copies thresholds and probabilities to the device (synchronous). */
+rsr_status rsr_model_create(rsr_ctx* ctx, int32_t n, int32_t K, const double* p,
+                            rsr_model** out);
+rsr_status rsr_model_destroy(rsr_model* model);
+
+/* Reference states for one target level (section 2.2, sets L(m') and U(m')):
+ * lower = host [R_L][n] uint8 states, each certifying S < level for every
+ * x <= row; upper = host [R_U][n], each certifying S >= level for every
+ * x >= row.  Rows need not be antichains: duplicates and dominated rows are
+ * legal.  R_L = 0 or R_U = 0 is legal (nothing matches on that side).
+ * EINVAL on a state >= K.  The handle holds packed device copies and can be
+ * reused with any model of the same n and K (section 5). */
+rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower,
+                           int64_t R_L, const uint8_t* upper, int64_t R_U, rsr_refs** out);
+rsr_status rsr_refs_destroy(rsr_refs* refs);
+
+/* System function handle: copies the graph to the device.  EINVAL on a node
+ * id out of range, source == sink, or level outside 1..K-1. */
+rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* desc, rsr_system** out);
+rsr_status rsr_system_destroy(rsr_system* sys);
+
+/* ---- hot path ------------------------------------------------------------ */
+
+/* Draws samples first_sample .. first_sample+N-1 of the model into
+ * d_samples (device [W][N] u32, layout above).  The 32-bit uniform word of
+ * component i of sample h is word (i mod 4) of Philox4x32-10 (Salmon et al.,
+ * SC'11) with counter (i div 4, low32(h), high32(h), stream_id) and key
+ * (low32(seed), high32(seed)); the state is then set by the thresholds of
+ * rsr_thresholds.  Any sample range can therefore be drawn independently and
+ * reproduced on any device or host.  EINVAL: N <= 0, NULL pointer. */
+rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint32_t stream_id,
+                      uint64_t first_sample, int64_t N, uint32_t* d_samples);
+
+/* Dominance classification (section 3.3, Algorithm 1).  For each sample h:
+ *   RSR_LABEL: bit0 of d_flags[h] = some lower row r has x_h <= r;
+ *              bit1 = some upper row r has x_h >= r, tested only when bit0 is
+ *              clear (Algorithm 1 gives the lower set precedence), else 0.
+ *   RSR_COUNT: both bits exact; if d_match is not NULL, d_match[2h] and
+ *              d_match[2h+1] receive the number of matching lower and upper
+ *              rows (u32, device [N][2]).
+ * form selects the kernel: RSR_POPCOUNT (bit-packed AND-NOT on the vector
+ * ALU), RSR_MFMA (int8 matrix-core contraction of eq. violation_matrix, COUNT
+ * and LABEL modes alike), RSR_AUTO (the faster one for this shape).  Every
+ * form returns identical outputs.  EINVAL: refs built for another n/K,
+ * N <= 0, NULL d_flags. */
+rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_samples,
+                        int64_t N, int32_t mode, int32_t form, uint8_t* d_flags,
+                        uint32_t* d_match);
+
+/* Stage-2 evaluation of the system function (section 3.5).  d_Y (device [N]
+ * u8) receives, for RSR_UNKNOWN_ONLY: 0 for a lower-flagged sample (bit0),
+ * 1 for an upper-flagged one (bit1 without bit0), Phi(x_h) for the others;
+ * for RSR_ALL: Phi(x_h) for every sample (plain Monte Carlo; d_flags may then
+ * be NULL).  Phi is evaluated by a batched breadth-first search on the device.
+ * d_n_evaluated (device u64, may be NULL) receives the number of Phi
+ * evaluations.  EINVAL: system built for another n/K, N <= 0. */
+rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples,
+                            int64_t N, const uint8_t* d_flags, int32_t which, uint8_t* d_Y,
+                            uint64_t* d_n_evaluated);
+
+/* Reduces flags (and Y, if not NULL) to counts on the device, copies them to
+ * the host, synchronises the stream and fills *out as rsr_estimate_t says.
+ * With d_Y == NULL, n_u_up = 0 and P, se, cov are NaN (bounds only). */
+rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
+                        rsr_estimate_t* out);
+
+/* Score-function partials of P = E[Y] with respect to the state
+ * probabilities (independent components make P multilinear in them):
+ *   c[i][s] = #{h : Y_h = 1 and x_{h,i} = s}          (exact, u64)
+ *   G[i][s] = c[i][s] / (N * p[i][s])  in fp32, 0 where p[i][s] = 0,
+ * computed as (float)c / ((float)N * (float)p).  For K = 2 with p[i][1] the
+ * survival probability, dP/dp_i = G[i][1] - G[i][0] (Birnbaum importance).
+ * d_G is device [n][K] f32; d_counts is device [n][K] u64 or NULL.
+ * d_samples must hold the samples of `model` that produced d_Y. */
+rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
+                    const uint8_t* d_Y, int64_t N, float* d_G, uint64_t* d_counts);
+
+/* ---- batched plan -------------------------------------------------------- */
+
+/* One job = the full hot path (sample, classify in LABEL mode, evaluate the
+ * unclassified samples, count, gradient) for one model against one
+ * reference set and system.  Buffers are caller-owned device memory:
+ * d_samples [W][N] u32, d_flags [N] u8, d_Y [N] u8, d_G [n][K] f32 (NULL:
+ * no gradient). */
+typedef struct {
+    const rsr_model* model;
+    const rsr_refs* refs;
+    const rsr_system* sys;
+    uint64_t seed;
+    uint32_t stream_id;
+    int64_t N;
+    uint32_t* d_samples;
+    uint8_t* d_flags;
+    uint8_t* d_Y;
+    float* d_G;
+} rsr_job;
+
+/* Builds a plan for n_jobs jobs: chooses a kernel configuration per job shape
+ * (timing candidates once per distinct shape unless `tune` is 0), orders the
+ * work, and records every launch of every job into one HIP graph.  The plan
+ * keeps the job array's pointers, so the handles and buffers must outlive it.
+ * Synchronous. */
+rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, int32_t tune,
+                           rsr_plan** out);
+/* Launches the plan's graph on the context stream (asynchronous). */
+rsr_status rsr_plan_run(rsr_plan* plan);
+/* Synchronises and copies the per-job estimates (host [n_jobs]) and, if
+ * G_host is not NULL, every job's gradient concatenated in job order (host,
+ * sum of n*K floats). */
+rsr_status rsr_plan_results(rsr_plan* plan, rsr_estimate_t* est, float* G_host);
+rsr_status rsr_plan_destroy(rsr_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSR_H */

@@ -1,0 +1,215 @@
+"""Thin Python layer over the C ABI: torch tensors supply device memory and the
+HIP stream; every step of the hot path runs in the library's HIP kernels.
+
+Functions keep the C names (rsr_sample, rsr_classify, rsr_eval_unknown,
+rsr_estimate, rsr_grad); the small classes own the C handles.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """rsr_ctx on a device, enqueueing on the given torch stream (default: the
+    current stream of that device)."""
+
+    def __init__(self, device=0, stream=None):
+        lib = A.lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the RSR library runs on the GPU only")
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = lib.rsr_ctx_create(int(device), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h))
+        if st != A.RSR_OK:
+            raise A.RSRError(st, "rsr_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().rsr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st):
+        A.check(self.h, st)
+
+
+class Model:
+    """rsr_model: independent components with state probabilities p [n][K] (fp64)."""
+
+    def __init__(self, ctx, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+        if p.ndim != 2:
+            raise ValueError("p must be [n][K]")
+        self.ctx = ctx
+        self.n, self.K = p.shape
+        self.p = p
+        h = ctypes.c_void_p()
+        ctx.check(A.lib().rsr_model_create(ctx.h, self.n, self.K, p.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def words(self):
+        return int(A.lib().rsr_words(self.n, self.K))
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().rsr_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Refs:
+    """rsr_refs: lower [R_L][n] and upper [R_U][n] uint8 reference states."""
+
+    def __init__(self, ctx, n, K, lower, upper):
+        lower = np.ascontiguousarray(np.asarray(lower, dtype=np.uint8).reshape(-1, n))
+        upper = np.ascontiguousarray(np.asarray(upper, dtype=np.uint8).reshape(-1, n))
+        self.ctx, self.n, self.K = ctx, int(n), int(K)
+        self.R_L, self.R_U = lower.shape[0], upper.shape[0]
+        h = ctypes.c_void_p()
+        ctx.check(A.lib().rsr_refs_create(
+            ctx.h, self.n, self.K, lower.ctypes.data_as(ctypes.c_void_p) if self.R_L else None,
+            self.R_L, upper.ctypes.data_as(ctypes.c_void_p) if self.R_U else None, self.R_U,
+            ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().rsr_refs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    """rsr_system: s-t connectivity of a graph at a level."""
+
+    def __init__(self, ctx, graph, K=2, level=1):
+        eu = np.ascontiguousarray(graph["edge_u"], dtype=np.int32)
+        ev = np.ascontiguousarray(graph["edge_v"], dtype=np.int32)
+        desc = A.rsr_system_desc(
+            A.RSR_SYS_ST_CONNECTIVITY, int(graph["n_nodes"]), eu.size, int(K),
+            eu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            int(graph["source"]), int(graph["sink"]), int(level))
+        self.ctx, self.n, self.K, self.level = ctx, eu.size, int(K), int(level)
+        h = ctypes.c_void_p()
+        ctx.check(A.lib().rsr_system_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().rsr_system_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def alloc_samples(ctx, model_or_n, K=None, N=0):
+    if isinstance(model_or_n, Model):
+        W = model_or_n.words
+    else:
+        W = int(A.lib().rsr_words(int(model_or_n), int(K)))
+    return torch.empty((W, int(N)), dtype=torch.int32, device=ctx.device)
+
+
+def rsr_sample(ctx, model, seed, stream_id, first, N, out=None):
+    out = alloc_samples(ctx, model, N=N) if out is None else out
+    ctx.check(A.lib().rsr_sample(ctx.h, model.h, int(seed), int(stream_id), int(first), int(N),
+                                 _ptr(out)))
+    return out
+
+
+def rsr_classify(ctx, refs, samples, N, mode=A.RSR_LABEL, form=A.RSR_AUTO, flags=None,
+                 match=None, want_match=False):
+    flags = torch.empty(int(N), dtype=torch.uint8, device=ctx.device) if flags is None else flags
+    if want_match and match is None:
+        match = torch.empty((int(N), 2), dtype=torch.int32, device=ctx.device)
+    ctx.check(A.lib().rsr_classify(ctx.h, refs.h, _ptr(samples), int(N), int(mode), int(form),
+                                   _ptr(flags), _ptr(match)))
+    return (flags, match) if want_match else flags
+
+
+def rsr_eval_unknown(ctx, system, samples, N, flags, which=A.RSR_UNKNOWN_ONLY, Y=None,
+                     n_evaluated=None):
+    Y = torch.empty(int(N), dtype=torch.uint8, device=ctx.device) if Y is None else Y
+    ctx.check(A.lib().rsr_eval_unknown(ctx.h, system.h, _ptr(samples), int(N), _ptr(flags),
+                                       int(which), _ptr(Y), _ptr(n_evaluated)))
+    return Y
+
+
+def rsr_estimate(ctx, flags, Y, N):
+    est = A.rsr_estimate_t()
+    ctx.check(A.lib().rsr_estimate(ctx.h, _ptr(flags), _ptr(Y), int(N), ctypes.byref(est)))
+    return est.as_dict()
+
+
+def rsr_grad(ctx, model, samples, Y, N, G=None, counts=None, want_counts=False):
+    G = torch.empty((model.n, model.K), dtype=torch.float32, device=ctx.device) if G is None else G
+    if want_counts and counts is None:
+        counts = torch.empty((model.n, model.K), dtype=torch.int64, device=ctx.device)
+    ctx.check(A.lib().rsr_grad(ctx.h, model.h, _ptr(samples), _ptr(Y), int(N), _ptr(G),
+                               _ptr(counts)))
+    return (G, counts) if want_counts else G
+
+
+class Buffers:
+    """Device buffers for one Stage-2 pass of N samples of an n x K model."""
+
+    def __init__(self, ctx, n, K, N):
+        W = int(A.lib().rsr_words(int(n), int(K)))
+        dev = ctx.device
+        self.N = int(N)
+        self.samples = torch.empty((W, self.N), dtype=torch.int32, device=dev)
+        self.flags = torch.empty(self.N, dtype=torch.uint8, device=dev)
+        self.Y = torch.empty(self.N, dtype=torch.uint8, device=dev)
+        self.G = torch.empty((n, K), dtype=torch.float32, device=dev)
+        self.n_eval = torch.zeros(1, dtype=torch.int64, device=dev)
+
+
+def stage2(ctx, model, refs, system, N, seed, stream_id=0, first=0, form=A.RSR_AUTO, grad=True,
+           buffers=None, estimate=True):
+    """One pass of the hot path: sample -> classify (LABEL) -> evaluate the
+    unclassified samples -> estimate (-> gradient).  Returns (estimate dict or
+    None, buffers)."""
+    b = buffers or Buffers(ctx, model.n, model.K, N)
+    lib, h = A.lib(), ctx.h
+    ctx.check(lib.rsr_sample(h, model.h, int(seed), int(stream_id), int(first), int(N),
+                             _ptr(b.samples)))
+    ctx.check(lib.rsr_classify(h, refs.h, _ptr(b.samples), int(N), A.RSR_LABEL, int(form),
+                               _ptr(b.flags), None))
+    ctx.check(lib.rsr_eval_unknown(h, system.h, _ptr(b.samples), int(N), _ptr(b.flags),
+                                   A.RSR_UNKNOWN_ONLY, _ptr(b.Y), _ptr(b.n_eval)))
+    if grad:
+        ctx.check(lib.rsr_grad(h, model.h, _ptr(b.samples), _ptr(b.Y), int(N), _ptr(b.G), None))
+    est = rsr_estimate(ctx, b.flags, b.Y, N) if estimate else None
+    return est, b

@@ -1,0 +1,152 @@
+// Stage-2 evaluation of the system function on the samples left
+// unclassified (section 3.5).
+//
+// k_label turns flags into Y (lower -> 0, upper -> 1) and appends the indices
+// of unclassified samples to a list: one ballot per wave, one atomic per wave
+// for the wave's slots.
+//
+// k_bfs evaluates s-t connectivity at a level on listed samples: one
+// wavefront per sample, the reachable set as a node bitmask in LDS, and
+// edge-parallel sweeps (lane l owns edges l, l+64, ...; an edge is usable when
+// the sample's thermometer plane `level` has its bit set).  A sweep marks both
+// ends of every usable edge with exactly one marked end; the search stops when
+// the sink is marked or a sweep changes nothing.  Each sweep either marks a
+// new node or ends the search, so there are at most n_nodes sweeps.  The grid
+// is sized on the host without knowing the number of unclassified samples
+// (it lives on the device), and waves stride over the list.
+#include "rsr_internal.h"
+
+namespace rsr {
+namespace {
+
+constexpr int kLabelBlock = 256;
+constexpr int kBfsBlock = 256;
+constexpr int kWavesPerBfsBlock = kBfsBlock / 64;
+constexpr int kMaxNodeWords = RSR_MAX_NODES / 32;
+
+__global__ __launch_bounds__(kLabelBlock) void k_label(const uint8_t* __restrict__ flags,
+                                                       int64_t N, uint8_t* __restrict__ Y,
+                                                       int32_t* __restrict__ list,
+                                                       unsigned long long* __restrict__ counter) {
+    const int64_t h = static_cast<int64_t>(blockIdx.x) * kLabelBlock + threadIdx.x;
+    const bool in = h < N;
+    const uint8_t f = in ? flags[h] : 1;
+    const bool unknown = (f & 3u) == 0u;
+    if (in) Y[h] = (f & 1u) ? 0 : ((f & 2u) ? 1 : 0);
+    const uint64_t mask = __ballot(unknown);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(mask)));
+    base = __shfl(base, leader);
+    if (unknown) {
+        const uint64_t below = mask & ((1ull << lane) - 1ull);
+        list[base + __popcll(below)] = static_cast<int32_t>(h);
+    }
+}
+
+__global__ __launch_bounds__(kBfsBlock) void k_bfs(
+    const uint32_t* __restrict__ xs, int64_t N, int PW, int plane, const uint32_t* __restrict__ edges,
+    int n_edges, int n_nodes, int source, int sink, const int32_t* __restrict__ list,
+    const unsigned long long* __restrict__ count_ptr, int which, uint8_t* __restrict__ Y,
+    unsigned long long* __restrict__ n_evaluated) {
+    __shared__ uint32_t s_edges[RSR_MAX_BITS];
+    __shared__ uint32_t s_reach[kWavesPerBfsBlock][kMaxNodeWords];
+
+    const int64_t total = which == RSR_ALL ? N : static_cast<int64_t>(*count_ptr);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_evaluated)
+        *n_evaluated = static_cast<unsigned long long>(total);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kWavesPerBfsBlock;
+    if (first >= total) return;  // uniform per block
+
+    for (int e = threadIdx.x; e < n_edges; e += kBfsBlock) s_edges[e] = edges[e];
+    __syncthreads();
+
+    const int node_words = (n_nodes + 31) >> 5;
+    const int edge_rounds = (n_edges + 63) >> 6;
+    uint32_t* reach = s_reach[wave];
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBfsBlock;
+
+    for (int64_t j = first + wave; j < total; j += stride) {
+        const int64_t h = which == RSR_ALL ? j : static_cast<int64_t>(list[j]);
+        // Usable-edge mask of this lane's edges.
+        uint64_t usable = 0;
+        for (int k = 0; k < edge_rounds; ++k) {
+            const int e = lane + 64 * k;
+            if (e < n_edges) {
+                const uint32_t word = xs[static_cast<int64_t>(plane * PW + (e >> 5)) * N + h];
+                usable |= static_cast<uint64_t>((word >> (e & 31)) & 1u) << k;
+            }
+        }
+        for (int wd = lane; wd < node_words; wd += 64) reach[wd] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) reach[source >> 5] = 1u << (source & 31);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        int result = 0;
+        while (true) {
+            bool changed = false;
+            uint64_t todo = usable;
+            while (todo) {
+                const int k = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+                todo &= todo - 1;
+                const uint32_t uv = s_edges[lane + 64 * k];
+                const uint32_t u = uv & 0xFFFFu, v = uv >> 16;
+                const uint32_t ru = (__hip_atomic_load(&reach[u >> 5], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WAVEFRONT) >> (u & 31)) & 1u;
+                const uint32_t rv = (__hip_atomic_load(&reach[v >> 5], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WAVEFRONT) >> (v & 31)) & 1u;
+                if (ru != rv) {
+                    const uint32_t w = ru ? v : u;
+                    atomicOr(&reach[w >> 5], 1u << (w & 31));
+                    changed = true;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t tw = __hip_atomic_load(&reach[sink >> 5], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const int hit = __builtin_amdgcn_readfirstlane(static_cast<int>((tw >> (sink & 31)) & 1u));
+            if (hit) {
+                result = 1;
+                break;
+            }
+            if (!__any(changed)) break;
+        }
+        if (lane == 0) Y[h] = static_cast<uint8_t>(result);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_label(hipStream_t st, const uint8_t* d_flags, int64_t N, int which,
+                        uint8_t* d_Y, int32_t* d_list, uint64_t* d_counter) {
+    (void)which;
+    const dim3 grid(static_cast<unsigned>((N + kLabelBlock - 1) / kLabelBlock));
+    hipLaunchKernelGGL(k_label, grid, dim3(kLabelBlock), 0, st, d_flags, N, d_Y, d_list,
+                       reinterpret_cast<unsigned long long*>(d_counter));
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const uint32_t* d_samples, int64_t N,
+                      const int32_t* d_list, const uint64_t* d_count, int which, uint8_t* d_Y,
+                      uint64_t* d_n_evaluated, int grid_blocks) {
+    const int64_t need = (N + kWavesPerBfsBlock - 1) / kWavesPerBfsBlock;
+    const int blocks = static_cast<int>(need < grid_blocks ? need : grid_blocks);
+    hipLaunchKernelGGL(k_bfs, dim3(blocks), dim3(kBfsBlock), 0, st, d_samples, N,
+                       plane_words(sys->n_edges), sys->level - 1, sys->d_edges, sys->n_edges,
+                       sys->n_nodes, sys->source, sys->sink, d_list,
+                       reinterpret_cast<const unsigned long long*>(d_count), which, d_Y,
+                       reinterpret_cast<unsigned long long*>(d_n_evaluated));
+    return hipGetLastError();
+}
+
+}  // namespace rsr

@@ -1,0 +1,459 @@
+// C ABI of the RSR Stage-2 library (declared in include/rsr.h): argument
+// validation, handle construction (threshold computation, reference-row
+// packing, graph upload), workspace management and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rsr_internal.h"
+
+using rsr::plane_words;
+using rsr::sample_words;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+rsr_status fail(rsr_ctx* ctx, rsr_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+rsr_status hip_fail(rsr_ctx* ctx, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return fail(ctx, e == hipErrorOutOfMemory ? RSR_ENOMEM : RSR_EHIP, m);
+}
+
+#define RSR_HIP(ctx, call)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+rsr_status validate_probs(rsr_ctx* ctx, int32_t n, int32_t K, const double* p) {
+    if (n <= 0 || K < 2) return fail(ctx, RSR_EINVAL, "n must be > 0 and K >= 2");
+    if (K > RSR_MAX_K) return fail(ctx, RSR_EUNSUPPORTED, "K exceeds RSR_MAX_K");
+    if (static_cast<int64_t>(n) * (K - 1) > RSR_MAX_BITS)
+        return fail(ctx, RSR_EUNSUPPORTED, "n*(K-1) exceeds RSR_MAX_BITS");
+    if (!p) return fail(ctx, RSR_EINVAL, "p is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        double sum = 0.0;
+        for (int32_t s = 0; s < K; ++s) {
+            const double v = p[static_cast<size_t>(i) * K + s];
+            if (!std::isfinite(v) || v < 0.0 || v > 1.0)
+                return fail(ctx, RSR_EINVAL,
+                            "p[" + std::to_string(i) + "][" + std::to_string(s) + "] not in [0,1]");
+            sum += v;
+        }
+        if (std::fabs(sum - 1.0) > 1e-9)
+            return fail(ctx, RSR_EINVAL, "row " + std::to_string(i) + " of p does not sum to 1");
+    }
+    return RSR_OK;
+}
+
+// Inverse-CDF thresholds: C[i][s-1] = min(floor(2^32 * cumulative), 2^32),
+// with the cumulative probability summed left to right in fp64.
+void compute_thresholds(int32_t n, int32_t K, const double* p, uint64_t* C) {
+    const double two32 = 4294967296.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double cum = 0.0;
+        for (int32_t s = 1; s < K; ++s) {
+            cum = cum + p[static_cast<size_t>(i) * K + (s - 1)];
+            const double f = std::floor(cum * two32);
+            uint64_t c = 0;
+            if (f >= two32)
+                c = 4294967296ull;
+            else if (f > 0.0)
+                c = static_cast<uint64_t>(f);
+            C[static_cast<size_t>(i) * (K - 1) + (s - 1)] = c;
+        }
+    }
+}
+
+rsr_status ensure_list(rsr_ctx* ctx, int64_t N) {
+    if (ctx->ws.list_cap >= N) return RSR_OK;
+    if (ctx->ws.list) {
+        RSR_HIP(ctx, hipFree(ctx->ws.list));
+        ctx->ws.list = nullptr;
+        ctx->ws.list_cap = 0;
+    }
+    RSR_HIP(ctx, hipMalloc(&ctx->ws.list, sizeof(int32_t) * static_cast<size_t>(N)));
+    ctx->ws.list_cap = N;
+    return RSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsr_status_str(rsr_status s) {
+    switch (s) {
+        case RSR_OK: return "RSR_OK";
+        case RSR_EINVAL: return "RSR_EINVAL";
+        case RSR_ENOMEM: return "RSR_ENOMEM";
+        case RSR_EHIP: return "RSR_EHIP";
+        case RSR_EUNSUPPORTED: return "RSR_EUNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+const char* rsr_last_error(const rsr_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+size_t rsr_words(int32_t n, int32_t K) {
+    if (n <= 0 || K < 2) return 0;
+    return static_cast<size_t>(sample_words(n, K));
+}
+
+rsr_status rsr_thresholds(int32_t n, int32_t K, const double* p, uint64_t* C) {
+    rsr_status st = validate_probs(nullptr, n, K, p);
+    if (st != RSR_OK) return st;
+    if (!C) return RSR_EINVAL;
+    compute_thresholds(n, K, p, C);
+    return RSR_OK;
+}
+
+rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
+    if (!out) return RSR_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return RSR_EHIP;
+    if (device < 0 || device >= count) return RSR_EINVAL;
+    rsr_ctx* ctx = new (std::nothrow) rsr_ctx();
+    if (!ctx) return RSR_ENOMEM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete ctx;
+        return RSR_EHIP;
+    }
+    ctx->cu_count = prop.multiProcessorCount;
+    rsr_status st = RSR_OK;
+    if (hipMalloc(&ctx->ws.counters, sizeof(uint64_t) * 16) != hipSuccess ||
+        hipMalloc(&ctx->ws.grad_acc, sizeof(uint64_t) * (RSR_MAX_BITS + 1)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ctx->ws.host_counts), sizeof(uint64_t) * 16,
+                      hipHostMallocDefault) != hipSuccess)
+        st = RSR_ENOMEM;
+    if (st != RSR_OK) {
+        rsr_ctx_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return RSR_OK;
+}
+
+rsr_status rsr_ctx_destroy(rsr_ctx* ctx) {
+    if (!ctx) return RSR_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->ws.counters) (void)hipFree(ctx->ws.counters);
+    if (ctx->ws.list) (void)hipFree(ctx->ws.list);
+    if (ctx->ws.grad_acc) (void)hipFree(ctx->ws.grad_acc);
+    if (ctx->ws.host_counts) (void)hipHostFree(ctx->ws.host_counts);
+    delete ctx;
+    return RSR_OK;
+}
+
+// ---- handles ---------------------------------------------------------------
+
+rsr_status rsr_model_create(rsr_ctx* ctx, int32_t n, int32_t K, const double* p,
+                            rsr_model** out) {
+    if (!ctx || !out) return RSR_EINVAL;
+    *out = nullptr;
+    rsr_status st = validate_probs(ctx, n, K, p);
+    if (st != RSR_OK) return st;
+    DeviceGuard g(ctx->device);
+    std::vector<uint64_t> C(static_cast<size_t>(n) * (K - 1));
+    compute_thresholds(n, K, p, C.data());
+    std::vector<float> pf(static_cast<size_t>(n) * K);
+    for (size_t i = 0; i < pf.size(); ++i) pf[i] = static_cast<float>(p[i]);
+    rsr_model* m = new (std::nothrow) rsr_model();
+    if (!m) return fail(ctx, RSR_ENOMEM, "host allocation");
+    m->ctx = ctx;
+    m->n = n;
+    m->K = K;
+    hipError_t e = hipMalloc(&m->d_thresh, sizeof(uint64_t) * C.size());
+    if (e == hipSuccess) e = hipMalloc(&m->d_p, sizeof(float) * pf.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_thresh, C.data(), sizeof(uint64_t) * C.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_p, pf.data(), sizeof(float) * pf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rsr_model_destroy(m);
+        return hip_fail(ctx, e, "rsr_model_create upload");
+    }
+    *out = m;
+    return RSR_OK;
+}
+
+rsr_status rsr_model_destroy(rsr_model* m) {
+    if (!m) return RSR_EINVAL;
+    DeviceGuard g(m->ctx->device);
+    if (m->d_thresh) (void)hipFree(m->d_thresh);
+    if (m->d_p) (void)hipFree(m->d_p);
+    delete m;
+    return RSR_OK;
+}
+
+rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower, int64_t R_L,
+                           const uint8_t* upper, int64_t R_U, rsr_refs** out) {
+    if (!ctx || !out) return RSR_EINVAL;
+    *out = nullptr;
+    if (n <= 0 || K < 2) return fail(ctx, RSR_EINVAL, "n must be > 0 and K >= 2");
+    if (K > RSR_MAX_K || static_cast<int64_t>(n) * (K - 1) > RSR_MAX_BITS)
+        return fail(ctx, RSR_EUNSUPPORTED, "n*(K-1) exceeds RSR_MAX_BITS or K > RSR_MAX_K");
+    if (R_L < 0 || R_U < 0) return fail(ctx, RSR_EINVAL, "negative row count");
+    if ((R_L > 0 && !lower) || (R_U > 0 && !upper))
+        return fail(ctx, RSR_EINVAL, "NULL reference rows with a non-zero count");
+    for (int64_t k = 0; k < R_L * n; ++k)
+        if (lower[k] >= K) return fail(ctx, RSR_EINVAL, "lower reference state >= K");
+    for (int64_t k = 0; k < R_U * n; ++k)
+        if (upper[k] >= K) return fail(ctx, RSR_EINVAL, "upper reference state >= K");
+    DeviceGuard g(ctx->device);
+    const int PW = plane_words(n);
+    const int W = sample_words(n, K);
+    const int WR = rsr::dom_row_words(W);
+    if (WR < 0) return fail(ctx, RSR_EUNSUPPORTED, "packed width not supported");
+    // Valid-bit mask per packed word (pad bits of each plane are 0).
+    std::vector<uint32_t> valid(W, 0u);
+    for (int j = 1; j < K; ++j)
+        for (int i = 0; i < n; ++i) valid[(j - 1) * PW + i / 32] |= 1u << (i % 32);
+    auto pack = [&](const uint8_t* row, uint32_t* dst, bool complement) {
+        for (int w = 0; w < WR; ++w) dst[w] = 0u;
+        for (int j = 1; j < K; ++j)
+            for (int i = 0; i < n; ++i)
+                if (row[i] >= j) dst[(j - 1) * PW + i / 32] |= 1u << (i % 32);
+        if (complement)
+            for (int w = 0; w < W; ++w) dst[w] = ~dst[w] & valid[w];
+    };
+    std::vector<uint32_t> lo(static_cast<size_t>(R_L) * WR), up(static_cast<size_t>(R_U) * WR);
+    for (int64_t r = 0; r < R_L; ++r) pack(lower + r * n, lo.data() + r * WR, true);
+    for (int64_t r = 0; r < R_U; ++r) pack(upper + r * n, up.data() + r * WR, false);
+
+    rsr_refs* refs = new (std::nothrow) rsr_refs();
+    if (!refs) return fail(ctx, RSR_ENOMEM, "host allocation");
+    refs->ctx = ctx;
+    refs->n = n;
+    refs->K = K;
+    refs->W = W;
+    refs->WR = WR;
+    refs->R_L = R_L;
+    refs->R_U = R_U;
+    hipError_t e = hipSuccess;
+    if (R_L > 0) {
+        e = hipMalloc(&refs->d_lower_nbits, sizeof(uint32_t) * lo.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(refs->d_lower_nbits, lo.data(), sizeof(uint32_t) * lo.size(),
+                          hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && R_U > 0) {
+        e = hipMalloc(&refs->d_upper_bits, sizeof(uint32_t) * up.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(refs->d_upper_bits, up.data(), sizeof(uint32_t) * up.size(),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        rsr_refs_destroy(refs);
+        return hip_fail(ctx, e, "rsr_refs_create upload");
+    }
+    *out = refs;
+    return RSR_OK;
+}
+
+rsr_status rsr_refs_destroy(rsr_refs* refs) {
+    if (!refs) return RSR_EINVAL;
+    DeviceGuard g(refs->ctx->device);
+    if (refs->d_lower_nbits) (void)hipFree(refs->d_lower_nbits);
+    if (refs->d_upper_bits) (void)hipFree(refs->d_upper_bits);
+    if (refs->d_lower_i8) (void)hipFree(refs->d_lower_i8);
+    if (refs->d_upper_i8) (void)hipFree(refs->d_upper_i8);
+    delete refs;
+    return RSR_OK;
+}
+
+rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system** out) {
+    if (!ctx || !out || !d) return RSR_EINVAL;
+    *out = nullptr;
+    if (d->kind != RSR_SYS_ST_CONNECTIVITY)
+        return fail(ctx, RSR_EUNSUPPORTED, "only RSR_SYS_ST_CONNECTIVITY is supported");
+    if (d->n_nodes < 2 || d->n_edges <= 0 || d->K < 2 || !d->edge_u || !d->edge_v)
+        return fail(ctx, RSR_EINVAL, "bad graph size or NULL edge arrays");
+    if (d->n_nodes > RSR_MAX_NODES || d->K > RSR_MAX_K ||
+        static_cast<int64_t>(d->n_edges) * (d->K - 1) > RSR_MAX_BITS)
+        return fail(ctx, RSR_EUNSUPPORTED, "graph exceeds RSR_MAX_NODES / RSR_MAX_BITS");
+    if (d->source < 0 || d->source >= d->n_nodes || d->sink < 0 || d->sink >= d->n_nodes ||
+        d->source == d->sink)
+        return fail(ctx, RSR_EINVAL, "source/sink out of range or equal");
+    if (d->level < 1 || d->level > d->K - 1) return fail(ctx, RSR_EINVAL, "level not in 1..K-1");
+    std::vector<uint32_t> packed(d->n_edges);
+    for (int e = 0; e < d->n_edges; ++e) {
+        const int32_t u = d->edge_u[e], v = d->edge_v[e];
+        if (u < 0 || u >= d->n_nodes || v < 0 || v >= d->n_nodes)
+            return fail(ctx, RSR_EINVAL, "edge endpoint out of range");
+        packed[e] = static_cast<uint32_t>(u) | (static_cast<uint32_t>(v) << 16);
+    }
+    DeviceGuard g(ctx->device);
+    rsr_system* s = new (std::nothrow) rsr_system();
+    if (!s) return fail(ctx, RSR_ENOMEM, "host allocation");
+    s->ctx = ctx;
+    s->n_nodes = d->n_nodes;
+    s->n_edges = d->n_edges;
+    s->K = d->K;
+    s->level = d->level;
+    s->source = d->source;
+    s->sink = d->sink;
+    hipError_t e = hipMalloc(&s->d_edges, sizeof(uint32_t) * packed.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(s->d_edges, packed.data(), sizeof(uint32_t) * packed.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rsr_system_destroy(s);
+        return hip_fail(ctx, e, "rsr_system_create upload");
+    }
+    *out = s;
+    return RSR_OK;
+}
+
+rsr_status rsr_system_destroy(rsr_system* s) {
+    if (!s) return RSR_EINVAL;
+    DeviceGuard g(s->ctx->device);
+    if (s->d_edges) (void)hipFree(s->d_edges);
+    delete s;
+    return RSR_OK;
+}
+
+// ---- hot path ----------------------------------------------------------------
+
+rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint32_t stream_id,
+                      uint64_t first_sample, int64_t N, uint32_t* d_samples) {
+    if (!ctx) return RSR_EINVAL;
+    if (!model || !d_samples) return fail(ctx, RSR_EINVAL, "NULL model or d_samples");
+    if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
+    DeviceGuard g(ctx->device);
+    RSR_HIP(ctx, rsr::launch_sample(ctx->stream, model, seed, stream_id, first_sample, N, d_samples));
+    return RSR_OK;
+}
+
+rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_samples, int64_t N,
+                        int32_t mode, int32_t form, uint8_t* d_flags, uint32_t* d_match) {
+    if (!ctx) return RSR_EINVAL;
+    if (!refs || !d_samples || !d_flags) return fail(ctx, RSR_EINVAL, "NULL argument");
+    if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
+    if (mode != RSR_LABEL && mode != RSR_COUNT) return fail(ctx, RSR_EINVAL, "bad mode");
+    if (form != RSR_AUTO && form != RSR_POPCOUNT && form != RSR_MFMA)
+        return fail(ctx, RSR_EINVAL, "bad form");
+    if (refs->ctx->device != ctx->device) return fail(ctx, RSR_EINVAL, "refs on another device");
+    DeviceGuard g(ctx->device);
+    if (form == RSR_MFMA) {
+        return fail(ctx, RSR_EUNSUPPORTED, "MFMA form not built");
+    }
+    RSR_HIP(ctx, rsr::launch_dom_bits(ctx->stream, refs, d_samples, N, mode, d_flags,
+                                      mode == RSR_COUNT ? d_match : nullptr));
+    return RSR_OK;
+}
+
+rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples,
+                            int64_t N, const uint8_t* d_flags, int32_t which, uint8_t* d_Y,
+                            uint64_t* d_n_evaluated) {
+    if (!ctx) return RSR_EINVAL;
+    if (!sys || !d_samples || !d_Y) return fail(ctx, RSR_EINVAL, "NULL argument");
+    if (N <= 0 || N > 0x7FFFFFFFll) return fail(ctx, RSR_EINVAL, "N must be in 1..2^31-1");
+    if (which != RSR_UNKNOWN_ONLY && which != RSR_ALL) return fail(ctx, RSR_EINVAL, "bad which");
+    if (which == RSR_UNKNOWN_ONLY && !d_flags)
+        return fail(ctx, RSR_EINVAL, "d_flags is NULL with RSR_UNKNOWN_ONLY");
+    DeviceGuard g(ctx->device);
+    uint64_t* counter = ctx->ws.counters + 8;
+    if (which == RSR_UNKNOWN_ONLY) {
+        rsr_status st = ensure_list(ctx, N);
+        if (st != RSR_OK) return st;
+        RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, counter, 1, 0));
+        RSR_HIP(ctx, rsr::launch_label(ctx->stream, d_flags, N, which, d_Y, ctx->ws.list, counter));
+    }
+    RSR_HIP(ctx, rsr::launch_bfs(ctx->stream, sys, d_samples, N, ctx->ws.list, counter, which, d_Y,
+                                 d_n_evaluated, ctx->cu_count * 8));
+    return RSR_OK;
+}
+
+rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
+                        rsr_estimate_t* out) {
+    if (!ctx) return RSR_EINVAL;
+    if (!d_flags || !out) return fail(ctx, RSR_EINVAL, "NULL argument");
+    if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
+    DeviceGuard g(ctx->device);
+    RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, ctx->ws.counters, 5, 0));
+    RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters));
+    RSR_HIP(ctx, hipMemcpyAsync(ctx->ws.host_counts, ctx->ws.counters, sizeof(uint64_t) * 5,
+                                hipMemcpyDeviceToHost, ctx->stream));
+    RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const uint64_t* c = ctx->ws.host_counts;
+    out->n_L = c[0];
+    out->n_U = c[1];
+    out->n_u = c[2];
+    out->n_both = c[3];
+    out->n_u_up = c[4];
+    out->N = static_cast<uint64_t>(N);
+    const double Nd = static_cast<double>(N);
+    out->p_L = static_cast<double>(out->n_L) / Nd;
+    out->p_U = static_cast<double>(out->n_U) / Nd;
+    out->p_u = static_cast<double>(out->n_u) / Nd;
+    if (!d_Y) {
+        out->P = out->se = out->cov = std::nan("");
+        return RSR_OK;
+    }
+    const double P = static_cast<double>(out->n_U + out->n_u_up) / Nd;
+    out->P = P;
+    out->se = std::sqrt(P * (1.0 - P) / Nd);
+    out->cov = P > 0.0 ? std::sqrt((1.0 - P) / (Nd * P)) : HUGE_VAL;
+    return RSR_OK;
+}
+
+rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
+                    const uint8_t* d_Y, int64_t N, float* d_G, uint64_t* d_counts) {
+    if (!ctx) return RSR_EINVAL;
+    if (!model || !d_samples || !d_Y || !d_G) return fail(ctx, RSR_EINVAL, "NULL argument");
+    if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
+    DeviceGuard g(ctx->device);
+    const int W = sample_words(model->n, model->K);
+    RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, ctx->ws.grad_acc, W * 32 + 1, 0));
+    RSR_HIP(ctx, rsr::launch_grad(ctx->stream, model, d_samples, d_Y, N, ctx->ws.grad_acc, d_G,
+                                  d_counts));
+    return RSR_OK;
+}
+
+// ---- batched plan (not yet built) ---------------------------------------------
+
+rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, int32_t tune,
+                           rsr_plan** out) {
+    (void)jobs;
+    (void)n_jobs;
+    (void)tune;
+    if (out) *out = nullptr;
+    return fail(ctx, RSR_EUNSUPPORTED, "batched plan not built");
+}
+rsr_status rsr_plan_run(rsr_plan* plan) { return plan ? RSR_EUNSUPPORTED : RSR_EINVAL; }
+rsr_status rsr_plan_results(rsr_plan* plan, rsr_estimate_t* est, float* G_host) {
+    (void)est;
+    (void)G_host;
+    return plan ? RSR_EUNSUPPORTED : RSR_EINVAL;
+}
+rsr_status rsr_plan_destroy(rsr_plan* plan) { return plan ? RSR_EUNSUPPORTED : RSR_EINVAL; }
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+"""GPU parity: every output of the HIP path against the plain CPU oracle on the
+same seeded inputs.  Integer outputs (samples, flags, match counts, Y, counts,
+estimates) must be bit-exact; the fp32 gradient must be within 1e-5 relative
+of the fp64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_17066_amd as R
+import workloads as WL
+from helpers import pad_bits, unpack_states
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-5
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _sample(ctx, p, seed, stream, first, N):
+    m = R.Model(ctx, p)
+    xs = R.rsr_sample(ctx, m, seed, stream, first, N)
+    return m, xs
+
+
+# ---------------------------------------------------------------- sampler ----
+
+@pytest.mark.parametrize("n,K,N,first,stream", [
+    (20, 2, 1000, 0, 0),
+    (295, 2, 4099, 12345, 7),
+    (37, 5, 777, (1 << 32) - 300, 3),
+    (64, 3, 513, 0, 0),
+    (1, 2, 65, 5, 0),
+    (1250, 2, 300, 99, 1),
+])
+def test_sample_bit_identical(rsr_ctx, n, K, N, first, stream):
+    rng = np.random.default_rng(n * 100 + K)
+    p = rng.dirichlet(np.ones(K), size=n)
+    p[0] = 0.0
+    p[0, K - 1] = 1.0          # a component that is always in the top state
+    if n > 1:
+        p[1] = 0.0
+        p[1, 0] = 1.0          # and one that is always in state 0
+    seed = 0x123456789ABCDEF ^ n
+    m, xs = _sample(rsr_ctx, p, seed, stream, first, N)
+    words = _np(xs)
+    assert words.shape == (m.words, N)
+    assert pad_bits(words, n, K) == 0
+    got = unpack_states(words, n, K)
+    want = oracle.sample(p, seed, stream, first, N)
+    np.testing.assert_array_equal(got, want)
+
+
+# ------------------------------------------------------------- classifier ----
+
+def _classify_both(ctx, cfg, N, lower, upper, level=1):
+    n, K = cfg["n"], cfg["K"]
+    p = cfg["p"]
+    m, xs = _sample(ctx, p, cfg["seed"], cfg["stream"], 0, N)
+    refs = R.Refs(ctx, n, K, lower, upper)
+    fl = R.rsr_classify(ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT)
+    fc, mt = R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, R.RSR_POPCOUNT, want_match=True)
+    x = oracle.sample(p, cfg["seed"], cfg["stream"], 0, N)
+    ol, _, _ = oracle.classify(lower, upper, x, mode=0)
+    oc, mL, mU = oracle.classify(lower, upper, x, mode=1)
+    return (_np(fl), _np(fc), _np(mt).view(np.uint32)), (ol, oc, mL, mU), (m, xs, refs, x)
+
+
+def _assert_classify(got, want):
+    fl, fc, mt = got
+    ol, oc, mL, mU = want
+    np.testing.assert_array_equal(fl, ol)
+    np.testing.assert_array_equal(fc, oc)
+    np.testing.assert_array_equal(mt[:, 0], mL)
+    np.testing.assert_array_equal(mt[:, 1], mU)
+
+
+def test_classify_tiny_complete_refs(rsr_ctx):
+    cfg = WL.configs.tiny(N=100_000)
+    got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], cfg["lower"], cfg["upper"])
+    _assert_classify(got, want)
+    assert int((got[0] & 3 == 0).sum()) == 0   # complete reference sets leave nothing unclassified
+
+
+def test_classify_graph2_subset(rsr_ctx):
+    cfg = WL.configs.graph2(N=30_011)
+    lower, upper = cfg["lower"][:3000], cfg["upper"][:2500]
+    got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], lower, upper)
+    _assert_classify(got, want)
+
+
+def test_classify_bernoulli_rows_both_sides(rsr_ctx):
+    cfg = WL.configs.scaling(N=20_000, R_U=1500, R_L=1700)
+    got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], cfg["lower"], cfg["upper"])
+    _assert_classify(got, want)
+
+
+def test_classify_bernoulli_dense_matches(rsr_ctx):
+    # Denser lower rows make lower matches common, so both-flag samples and the
+    # lower precedence of the LABEL mode are exercised.
+    n = 40
+    rng = np.random.default_rng(5)
+    p = WL.configs.binary_model(rng.uniform(0.2, 0.6, n))
+    cfg = {"n": n, "K": 2, "p": p, "seed": 77, "stream": 2}
+    lower = WL.bernoulli_rows(500, n, 0.8, seed=6)
+    upper = WL.bernoulli_rows(400, n, 0.15, seed=7)
+    got, want, _ = _classify_both(rsr_ctx, cfg, 9_999, lower, upper)
+    _assert_classify(got, want)
+    assert int((want[1] == 3).sum()) > 0
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_classify_multistate_levels(rsr_ctx, level):
+    cfg = WL.configs.multi(N=10_007, R_per_level=4000)
+    lv = cfg["levels"][level]
+    got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], lv["lower"], lv["upper"])
+    _assert_classify(got, want)
+
+
+@pytest.mark.parametrize("RL,RU,N", [(0, 50, 1000), (60, 0, 1000), (0, 0, 100), (33, 31, 1),
+                                     (70, 65, 63), (70, 65, 65)])
+def test_classify_edge_shapes(rsr_ctx, RL, RU, N):
+    n, K = 70, 3
+    rng = np.random.default_rng(RL * 7 + RU + N)
+    p = rng.dirichlet([1.0, 1.0, 3.0], size=n)
+    cfg = {"n": n, "K": K, "p": p, "seed": 9, "stream": 0}
+    lower = rng.integers(1, 3, size=(RL, n)).astype(np.uint8)
+    upper = (rng.random((RU, n)) < 0.1).astype(np.uint8)
+    if RL > 2:
+        lower[1] = lower[0]     # duplicate rows are legal
+    got, want, _ = _classify_both(rsr_ctx, cfg, N, lower, upper)
+    _assert_classify(got, want)
+
+
+# ---------------------------------------------------- eval / estimate / grad --
+
+def _full_path(ctx, cfg, N, lower, upper, level=1):
+    n, K = cfg["n"], cfg["K"]
+    g = cfg["graph"]
+    m = R.Model(ctx, cfg["p"])
+    refs = R.Refs(ctx, n, K, lower, upper)
+    sysm = R.System(ctx, g, K=K, level=level)
+    est, buf = R.stage2(ctx, m, refs, sysm, N, cfg["seed"], stream_id=cfg["stream"])
+    Gc = R.rsr_grad(ctx, m, buf.samples, buf.Y, N, want_counts=True)
+    return est, buf, Gc, (m, refs, sysm)
+
+
+def _oracle_path(cfg, N, lower, upper, level=1):
+    x = oracle.sample(cfg["p"], cfg["seed"], cfg["stream"], 0, N)
+    fl, _, _ = oracle.classify(lower, upper, x, mode=0)
+    Y, nev = oracle.eval_unknown(cfg["graph"], x, fl, which=0, level=level)
+    cnt = oracle.counts(fl, Y)
+    est = oracle.estimate(cnt)
+    c, G = oracle.grad(cfg["p"], x, Y)
+    return x, fl, Y, nev, cnt, est, c, G
+
+
+def _assert_estimate(est, cnt, oest):
+    for k, name in enumerate(oracle.COUNT_NAMES):
+        assert est[name] == int(cnt[k]), name
+    for k, name in enumerate(oracle.EST_NAMES):
+        assert est[name] == oest[k] or (np.isinf(est[name]) and np.isinf(oest[k])), name
+
+
+def _assert_grad(G, counts, c, Gref):
+    np.testing.assert_array_equal(counts.view(np.uint64), c)
+    G = G.astype(np.float64)
+    nz = Gref != 0
+    rel = np.abs(G[nz] - Gref[nz]) / np.abs(Gref[nz])
+    assert rel.max(initial=0.0) <= GRAD_RTOL
+    assert np.all(G[~nz] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["tiny", "graph2"])
+def test_full_path_bit_exact(rsr_ctx, name):
+    if name == "tiny":
+        cfg = WL.configs.tiny(N=100_000)
+        lower, upper = cfg["lower"][:-4], cfg["upper"][:-20]   # partial refs -> unknowns
+    else:
+        cfg = WL.configs.graph2(N=50_000)
+        lower, upper = cfg["lower"][:2000], cfg["upper"][:2000]
+    N = cfg["N"]
+    est, buf, (G, counts), _ = _full_path(rsr_ctx, cfg, N, lower, upper)
+    x, fl, Y, nev, cnt, oest, c, Gref = _oracle_path(cfg, N, lower, upper)
+    np.testing.assert_array_equal(_np(buf.flags), fl)
+    np.testing.assert_array_equal(_np(buf.Y), Y)
+    assert int(_np(buf.n_eval)[0]) == nev
+    assert nev > 0
+    _assert_estimate(est, cnt, oest)
+    _assert_grad(_np(G), _np(counts), c, Gref)
+
+
+def test_eval_all_is_plain_mc(rsr_ctx):
+    cfg = WL.configs.graph2(N=20_000)
+    N = cfg["N"]
+    m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, N)
+    sysm = R.System(rsr_ctx, cfg["graph"])
+    nev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    Y = R.rsr_eval_unknown(rsr_ctx, sysm, xs, N, None, which=R.RSR_ALL, n_evaluated=nev)
+    x = oracle.sample(cfg["p"], cfg["seed"], 0, 0, N)
+    Yo, _ = oracle.eval_unknown(cfg["graph"], x, None, which=1)
+    np.testing.assert_array_equal(_np(Y), Yo)
+    assert int(_np(nev)[0]) == N
+
+
+def test_multistate_full_path(rsr_ctx):
+    cfg = WL.configs.multi(N=20_000, R_per_level=4000)
+    N = cfg["N"]
+    for level in (1, 2):
+        lv = cfg["levels"][level]
+        est, buf, (G, counts), _ = _full_path(rsr_ctx, cfg, N, lv["lower"], lv["upper"], level)
+        x, fl, Y, nev, cnt, oest, c, Gref = _oracle_path(cfg, N, lv["lower"], lv["upper"], level)
+        np.testing.assert_array_equal(_np(buf.flags), fl)
+        np.testing.assert_array_equal(_np(buf.Y), Y)
+        _assert_estimate(est, cnt, oest)
+        _assert_grad(_np(G), _np(counts), c, Gref)
+
+
+def test_estimate_bounds_only(rsr_ctx):
+    cfg = WL.configs.tiny(N=5000)
+    m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, cfg["N"])
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"][:5], cfg["upper"][:5])
+    fl = R.rsr_classify(rsr_ctx, refs, xs, cfg["N"])
+    est = R.rsr_estimate(rsr_ctx, fl, None, cfg["N"])
+    cnt = oracle.counts(_np(fl))
+    oest = oracle.estimate(cnt, has_Y=False)
+    assert est["n_u_up"] == 0
+    assert np.isnan(est["P"]) and np.isnan(oest[3])
+    assert est["p_L"] == oest[0] and est["p_U"] == oest[1] and est["p_u"] == oest[2]
+
+
+# ------------------------------------------------ full-size sampled checks ----
+
+def test_graph2_full_size_sampled(rsr_ctx):
+    """The benchmark configuration (119 nodes / 295 edges, 1e4 + 1e4 rows,
+    N = 1e6), checked on 3000 sampled indices one by one."""
+    cfg = WL.configs.graph2()
+    N = cfg["N"]
+    m = R.Model(rsr_ctx, cfg["p"])
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
+    sysm = R.System(rsr_ctx, cfg["graph"])
+    est, buf = R.stage2(rsr_ctx, m, refs, sysm, N, cfg["seed"])
+    G, counts = R.rsr_grad(rsr_ctx, m, buf.samples, buf.Y, N, want_counts=True)
+    rng = np.random.default_rng(123)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 3000), [0, N - 1]])).astype(np.uint64)
+    x = oracle.sample_at(cfg["p"], cfg["seed"], 0, idx)
+    got_x = unpack_states(_np(buf.samples)[:, idx.astype(np.int64)], cfg["n"], 2)
+    np.testing.assert_array_equal(got_x, x)
+    fl, _, _ = oracle.classify(cfg["lower"], cfg["upper"], x, mode=0)
+    np.testing.assert_array_equal(_np(buf.flags)[idx.astype(np.int64)], fl)
+    Y, _ = oracle.eval_unknown(cfg["graph"], x, fl, which=0)
+    np.testing.assert_array_equal(_np(buf.Y)[idx.astype(np.int64)], Y)
+    # Properties that hold at any size.
+    assert est["N"] == N
+    assert est["n_L"] + est["n_U"] + est["n_u"] == N
+    assert est["n_both"] == 0
+    assert est["p_U"] <= est["P"] <= 1.0 - est["p_L"]
+    c = _np(counts).view(np.uint64)
+    n_y1 = est["n_U"] + est["n_u_up"]
+    assert np.all(c.sum(axis=1) == n_y1)
+    G = _np(G).astype(np.float64)
+    Gexp = c / (N * cfg["p"])
+    nz = c > 0          # a bridge edge in state 0 never has Y = 1
+    assert np.max(np.abs(G[nz] - Gexp[nz]) / Gexp[nz]) <= GRAD_RTOL
+    assert np.all(G[~nz] == 0.0)
+
+
+def test_scaling_full_size_sampled_counts(rsr_ctx):
+    """Kernel-only scaling workload (n = 295, 1e5 + 1e5 rows, N = 1e6) in
+    COUNT mode, exact match counts on 300 sampled samples."""
+    cfg = WL.configs.scaling()
+    N = cfg["N"]
+    m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, N)
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
+    fc, mt = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, R.RSR_POPCOUNT, want_match=True)
+    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT)
+    rng = np.random.default_rng(7)
+    idx = np.unique(rng.integers(0, N, 300)).astype(np.uint64)
+    x = oracle.sample_at(cfg["p"], cfg["seed"], 0, idx)
+    oc, mL, mU = oracle.classify(cfg["lower"], cfg["upper"], x, mode=1)
+    ol, _, _ = oracle.classify(cfg["lower"], cfg["upper"], x, mode=0)
+    ii = idx.astype(np.int64)
+    mt = _np(mt).view(np.uint32)
+    np.testing.assert_array_equal(_np(fc)[ii], oc)
+    np.testing.assert_array_equal(mt[ii, 0], mL)
+    np.testing.assert_array_equal(mt[ii, 1], mU)
+    np.testing.assert_array_equal(_np(fl)[ii], ol)
+
+
+def test_classify_deterministic(rsr_ctx):
+    cfg = WL.configs.graph2(N=100_000)
+    m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, cfg["N"])
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
+    a = _np(R.rsr_classify(rsr_ctx, refs, xs, cfg["N"]))
+    b = _np(R.rsr_classify(rsr_ctx, refs, xs, cfg["N"]))
+    np.testing.assert_array_equal(a, b)
