@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz 32-bit vector ops per second.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X dense int8 matrix-core peak (AMD's published figure, no sparsity).
+MFMA_I8_PEAK_OPS = 5.0e15
 
 
 def log(msg):
@@ -98,22 +100,37 @@ def main():
     label_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, label classify {label_ms:.3f} ms")
 
-    # Dominant kernel in COUNT mode (every test evaluated in full).
+    # Classification kernels timed alone (HIP events on the context stream).
     reps = max(3, min(args.steps, 10))
-    cev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
-    ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, R.RSR_COUNT, form, P(buf.flags),
-                               None))
-    for i in range(reps):
-        cev[i][0].record()
-        ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, R.RSR_COUNT, form,
-                                   P(buf.flags), None))
-        cev[i][1].record()
-    torch.cuda.synchronize()
-    count_ms = float(np.mean([a.elapsed_time(b) for a, b in cev]))
+
+    def time_classify(mode, f):
+        cev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+        ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, mode, f, P(buf.flags), None))
+        for i in range(reps):
+            cev[i][0].record()
+            ctx.check(lib.rsr_classify(h, refs.h, P(buf.samples), N, mode, f, P(buf.flags), None))
+            cev[i][1].record()
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in cev]))
+
     W = model.words
-    ops = float(tests) * W          # one 32-bit AND-OR per packed word per test
-    achieved = ops / (count_ms * 1e-3)
-    log(f"COUNT classify {count_ms:.3f} ms -> {achieved / 1e12:.2f} TOP/s")
+    KP = 64 * ((32 * W + 63) // 64)
+    kern = {}
+    for fname, f in (("popcount", R.RSR_POPCOUNT), ("mfma", R.RSR_MFMA)):
+        kern[fname] = {"count_ms": time_classify(R.RSR_COUNT, f),
+                       "label_ms": time_classify(R.RSR_LABEL, f)}
+    # Popcount form: one 32-bit AND-OR per packed word per test on the vector ALU.
+    kern["popcount"]["count_achieved"] = float(tests) * W / (kern["popcount"]["count_ms"] * 1e-3)
+    kern["popcount"]["count_frac"] = kern["popcount"]["count_achieved"] / VALU_PEAK_OPS
+    # Matrix-core form: 2 KP int8 operations per test (KP = packed bits rounded to 64).
+    kern["mfma"]["count_achieved"] = float(tests) * 2 * KP / (kern["mfma"]["count_ms"] * 1e-3)
+    kern["mfma"]["count_frac"] = kern["mfma"]["count_achieved"] / MFMA_I8_PEAK_OPS
+    for k, v in kern.items():
+        log(f"{k}: COUNT {v['count_ms']:.3f} ms ({v['count_frac'] * 100:.1f}% of peak), "
+            f"LABEL {v['label_ms']:.3f} ms")
+    dom = args.form if args.form != "auto" else "popcount"
+    count_ms = kern[dom]["count_ms"]
+    achieved = kern[dom]["count_achieved"]
     # Restore LABEL flags so the buffers hold a consistent pass.
     step()
     torch.cuda.synchronize()
@@ -144,16 +161,17 @@ def main():
             "P": est["P"], "p_u": est["p_u"], "se": est["se"],
         },
         "roofline": {
-            "kernel": "rsr_classify (COUNT mode, every test in full), same workload and launch",
-            "bound": "alu",
+            "kernel": f"rsr_classify {dom} form, COUNT mode (every test in full), same workload",
+            "bound": "alu" if dom == "popcount" else "mfma",
             "achieved": achieved / 1e12,
-            "peak": VALU_PEAK_OPS / 1e12,
+            "peak": (VALU_PEAK_OPS if dom == "popcount" else MFMA_I8_PEAK_OPS) / 1e12,
             "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_OPS,
+            "frac": achieved / (VALU_PEAK_OPS if dom == "popcount" else MFMA_I8_PEAK_OPS),
             "traffic": None,
-            "ops_per_test": W,
+            "ops_per_test": W if dom == "popcount" else 2 * KP,
             "kernel_ms": count_ms,
         },
+        "classify_forms": kern,
         "label_classify": {
             "kernel_ms": label_ms,
             "nominal_tests_per_s": tests / (label_ms * 1e-3),

@@ -1,14 +1,18 @@
 // Reductions: estimator counts (section 3.3.1) and the score-function
 // gradient counts.
 //
-// k_counts: one pass over flags (and Y) with per-thread counters, a wavefront
-// reduction and one 64-bit atomic per counter per wave.
+// Both reductions are two-pass and atomic-free: blocks write partial sums to a
+// workspace and a second kernel adds them in a fixed order, so results do not
+// depend on scheduling and no address is contended.
+//
+// k_counts: one pass over flags (and Y) with per-thread counters, wavefront
+// and block reductions, one partial row per block; k_counts_final adds rows.
 //
 // k_grad_bits: a[j][i] = #{h : Y_h = 1 and x_{h,i} >= j} for every thermometer
 // bit (plane j, component i).  Block column y = packed word w; each thread
-// walks a strided run of samples, keeps 32 per-bit counters of its masked
-// words, and the block adds them into a[w][*] with one atomic per bit per
-// wave.  Blocks in column 0 also count #{Y = 1}.
+// walks a strided run of samples (about 64) and keeps 32 per-bit counters of
+// its Y-masked words; the block reduces them to one partial row.  Blocks in
+// column 0 also count #{Y = 1}.
 // k_grad_finalize: c[i][s] = a[s][i] - a[s+1][i] (a[0][i] = #{Y = 1},
 // a[K][i] = 0), G[i][s] = (float)c / ((float)N * p[i][s]).
 #include "rsr_internal.h"
@@ -38,8 +42,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int6
 
 __global__ __launch_bounds__(kBlock) void k_counts(const uint8_t* __restrict__ flags,
                                                    const uint8_t* __restrict__ Y, int64_t N,
-                                                   unsigned long long* __restrict__ out) {
-    unsigned long long nL = 0, nU = 0, nu = 0, nb = 0, nuu = 0;
+                                                   unsigned long long* __restrict__ partial) {
+    // partial[block][0..4] = this block's n_L, n_U, n_u, n_both, n_u_up.
+    uint32_t nL = 0, nU = 0, nu = 0, nb = 0, nuu = 0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t h = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; h < N; h += stride) {
         const uint32_t f = flags[h];
@@ -51,24 +56,56 @@ __global__ __launch_bounds__(kBlock) void k_counts(const uint8_t* __restrict__ f
         nb += lo & up;
         if (unk && Y) nuu += Y[h] ? 1u : 0u;
     }
-    nL = wave_sum(nL);
-    nU = wave_sum(nU);
-    nu = wave_sum(nu);
-    nb = wave_sum(nb);
-    nuu = wave_sum(nuu);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&out[0], nL);
-        atomicAdd(&out[1], nU);
-        atomicAdd(&out[2], nu);
-        atomicAdd(&out[3], nb);
-        atomicAdd(&out[4], nuu);
+    __shared__ uint32_t red[kBlock / 64][5];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    nL = wave_sum32(nL);
+    nU = wave_sum32(nU);
+    nu = wave_sum32(nu);
+    nb = wave_sum32(nb);
+    nuu = wave_sum32(nuu);
+    if (lane == 0) {
+        red[wave][0] = nL;
+        red[wave][1] = nU;
+        red[wave][2] = nu;
+        red[wave][3] = nb;
+        red[wave][4] = nuu;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long s = 0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        partial[static_cast<int64_t>(blockIdx.x) * 8 + threadIdx.x] = s;
     }
 }
 
+// Sums the per-block partials of k_counts into out[0..4] (one block).
+__global__ __launch_bounds__(kBlock) void k_counts_final(const unsigned long long* __restrict__ partial,
+                                                         int blocks,
+                                                         unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[kBlock / 64][5];
+    unsigned long long v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < blocks; b += kBlock)
+        for (int k = 0; k < 5; ++k) v[k] += partial[static_cast<int64_t>(b) * 8 + k];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k < 5; ++k) {
+        v[k] = wave_sum(v[k]);
+        if (lane == 0) red[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long s = 0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Per-bit masked counts of one packed word column, written as per-block
+// partials: partial[(w * gridDim.x + bx) * 32 + b]; column 0 blocks also write
+// #{Y = 1} to ypart[bx].
 __global__ __launch_bounds__(kBlock) void k_grad_bits(const uint32_t* __restrict__ xs,
                                                       const uint8_t* __restrict__ Y, int64_t N,
-                                                      unsigned long long* __restrict__ acc,
-                                                      int W) {
+                                                      uint32_t* __restrict__ partial,
+                                                      uint32_t* __restrict__ ypart) {
     const int w = blockIdx.y;
     uint32_t c[32];
 #pragma unroll
@@ -83,30 +120,46 @@ __global__ __launch_bounds__(kBlock) void k_grad_bits(const uint32_t* __restrict
 #pragma unroll
         for (int b = 0; b < 32; ++b) c[b] += (v >> b) & 1u;
     }
-    const int lane = threadIdx.x & 63;
+    __shared__ uint32_t red[kBlock / 64][33];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int b = 0; b < 32; ++b) {
         const uint32_t s = wave_sum32(c[b]);
-        if (lane == 0 && s) atomicAdd(&acc[w * 32 + b], static_cast<unsigned long long>(s));
+        if (lane == 0) red[wave][b] = s;
     }
-    if (w == 0) {
-        const uint32_t s = wave_sum32(ny);
-        if (lane == 0 && s) atomicAdd(&acc[W * 32], static_cast<unsigned long long>(s));
+    const uint32_t sy = wave_sum32(ny);
+    if (lane == 0) red[wave][32] = sy;
+    __syncthreads();
+    if (threadIdx.x < 33) {
+        uint32_t s = 0;
+        for (int k = 0; k < kBlock / 64; ++k) s += red[k][threadIdx.x];
+        if (threadIdx.x < 32)
+            partial[(static_cast<int64_t>(w) * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = s;
+        else if (w == 0)
+            ypart[blockIdx.x] = s;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_grad_finalize(const unsigned long long* __restrict__ acc,
-                                                          const float* __restrict__ p, int n,
-                                                          int K, int PW, int W, int64_t N,
+__global__ __launch_bounds__(kBlock) void k_grad_finalize(const uint32_t* __restrict__ partial,
+                                                          const uint32_t* __restrict__ ypart,
+                                                          int bx, const float* __restrict__ p,
+                                                          int n, int K, int PW, int64_t N,
                                                           float* __restrict__ G,
                                                           unsigned long long* __restrict__ counts) {
     const int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= n * K) return;
     const int i = idx / K, s = idx % K;
+    // a(j) = #{h : Y_h = 1 and x_{h,i} >= j}; a(0) = #{Y = 1}; a(K) = 0.
     auto level_count = [&](int j) -> unsigned long long {
-        if (j == 0) return acc[W * 32];
-        if (j >= K) return 0ull;
-        return acc[((j - 1) * PW + (i >> 5)) * 32 + (i & 31)];
+        unsigned long long t = 0;
+        if (j == 0) {
+            for (int b = 0; b < bx; ++b) t += ypart[b];
+        } else if (j < K) {
+            const int w = (j - 1) * PW + (i >> 5);
+            const uint32_t* col = partial + static_cast<int64_t>(w) * bx * 32 + (i & 31);
+            for (int b = 0; b < bx; ++b) t += col[static_cast<int64_t>(b) * 32];
+        }
+        return t;
     };
     const unsigned long long cnt = level_count(s) - level_count(s + 1);
     const float pv = p[idx];
@@ -126,31 +179,38 @@ hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t 
 }
 
 hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
-                         uint64_t* d_counters) {
-    int64_t blocks = (N + kBlock * 8 - 1) / (kBlock * 8);
-    if (blocks > 2048) blocks = 2048;
+                         uint64_t* d_counters, uint64_t* d_partial) {
+    int64_t blocks = (N + kBlock * 16 - 1) / (kBlock * 16);
+    if (blocks > kMaxReduceBlocks) blocks = kMaxReduceBlocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_counts, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, d_flags,
-                       d_Y, N, reinterpret_cast<unsigned long long*>(d_counters));
+                       d_Y, N, reinterpret_cast<unsigned long long*>(d_partial));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_counts_final, dim3(1), dim3(kBlock), 0, st,
+                       reinterpret_cast<const unsigned long long*>(d_partial),
+                       static_cast<int>(blocks), reinterpret_cast<unsigned long long*>(d_counters));
     return hipGetLastError();
 }
 
 hipError_t launch_grad(hipStream_t st, const rsr_model* m, const uint32_t* d_samples,
-                       const uint8_t* d_Y, int64_t N, uint64_t* d_acc, float* d_G,
+                       const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
                        uint64_t* d_counts) {
     const int PW = plane_words(m->n);
     const int W = (m->K - 1) * PW;
-    int64_t bx = (N + kBlock * 16 - 1) / (kBlock * 16);
-    if (bx > 512) bx = 512;
+    // About 64 samples per thread, at most kMaxGradBlocks blocks per word column.
+    int64_t bx = (N + kBlock * 64 - 1) / (kBlock * 64);
+    if (bx > kMaxGradBlocks) bx = kMaxGradBlocks;
     if (bx < 1) bx = 1;
+    uint32_t* ypart = d_partial + static_cast<int64_t>(W) * bx * 32;
     hipLaunchKernelGGL(k_grad_bits, dim3(static_cast<unsigned>(bx), W), dim3(kBlock), 0, st,
-                       d_samples, d_Y, N, reinterpret_cast<unsigned long long*>(d_acc), W);
+                       d_samples, d_Y, N, d_partial, ypart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int total = m->n * m->K;
     hipLaunchKernelGGL(k_grad_finalize, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                       reinterpret_cast<const unsigned long long*>(d_acc), m->d_p, m->n, m->K, PW,
-                       W, N, d_G, reinterpret_cast<unsigned long long*>(d_counts));
+                       d_partial, ypart, static_cast<int>(bx), m->d_p, m->n, m->K, PW, N, d_G,
+                       reinterpret_cast<unsigned long long*>(d_counts));
     return hipGetLastError();
 }
 

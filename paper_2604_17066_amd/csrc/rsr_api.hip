@@ -147,7 +147,9 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
     ctx->cu_count = prop.multiProcessorCount;
     rsr_status st = RSR_OK;
     if (hipMalloc(&ctx->ws.counters, sizeof(uint64_t) * 16) != hipSuccess ||
-        hipMalloc(&ctx->ws.grad_acc, sizeof(uint64_t) * (RSR_MAX_BITS + 1)) != hipSuccess ||
+        hipMalloc(&ctx->ws.count_part, sizeof(uint64_t) * rsr::kMaxReduceBlocks * 8) != hipSuccess ||
+        hipMalloc(&ctx->ws.grad_part, sizeof(uint32_t) * (static_cast<size_t>(RSR_MAX_BITS) + 1) *
+                                          rsr::kMaxGradBlocks) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ctx->ws.host_counts), sizeof(uint64_t) * 16,
                       hipHostMallocDefault) != hipSuccess)
         st = RSR_ENOMEM;
@@ -166,7 +168,8 @@ rsr_status rsr_ctx_destroy(rsr_ctx* ctx) {
     else (void)hipDeviceSynchronize();
     if (ctx->ws.counters) (void)hipFree(ctx->ws.counters);
     if (ctx->ws.list) (void)hipFree(ctx->ws.list);
-    if (ctx->ws.grad_acc) (void)hipFree(ctx->ws.grad_acc);
+    if (ctx->ws.count_part) (void)hipFree(ctx->ws.count_part);
+    if (ctx->ws.grad_part) (void)hipFree(ctx->ws.grad_part);
     if (ctx->ws.host_counts) (void)hipHostFree(ctx->ws.host_counts);
     delete ctx;
     return RSR_OK;
@@ -248,6 +251,39 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     for (int64_t r = 0; r < R_L; ++r) pack(lower + r * n, lo.data() + r * WR, true);
     for (int64_t r = 0; r < R_U; ++r) pack(upper + r * n, up.data() + r * WR, false);
 
+    // Matrix-core operands: fragment-ordered 0/1 bytes and accumulator starts.
+    const int KS = (W * 32 + 63) / 64;
+    const bool with_mfma = KS <= rsr::kMaxMfmaSteps;
+    const int TL = static_cast<int>((R_L + 15) / 16), TU = static_cast<int>((R_U + 15) / 16);
+    std::vector<int8_t> lof, upf;
+    std::vector<int32_t> loc, upc;
+    if (with_mfma) {
+        auto frag = [&](const uint32_t* words, int64_t r, std::vector<int8_t>& dst) {
+            const int64_t T = r / 16;
+            const int rr = static_cast<int>(r % 16);
+            for (int k = 0; k < W * 32; ++k) {
+                if (!((words[k / 32] >> (k % 32)) & 1u)) continue;
+                const int s = k / 64, o = k % 64;
+                const int lane = (o / 16) * 16 + rr;
+                dst[((static_cast<size_t>(T) * KS + s) * 64 + lane) * 16 + (o % 16)] = 1;
+            }
+        };
+        lof.assign(static_cast<size_t>(TL) * KS * 1024, 0);
+        upf.assign(static_cast<size_t>(TU) * KS * 1024, 0);
+        loc.assign(static_cast<size_t>(TL) * 16, 1);
+        upc.assign(static_cast<size_t>(TU) * 16, 1);
+        for (int64_t r = 0; r < R_L; ++r) {
+            frag(lo.data() + r * WR, r, lof);
+            loc[r] = 0;
+        }
+        for (int64_t r = 0; r < R_U; ++r) {
+            frag(up.data() + r * WR, r, upf);
+            int pop = 0;
+            for (int w = 0; w < W; ++w) pop += __builtin_popcount(up[r * WR + w]);
+            upc[r] = -pop;
+        }
+    }
+
     rsr_refs* refs = new (std::nothrow) rsr_refs();
     if (!refs) return fail(ctx, RSR_ENOMEM, "host allocation");
     refs->ctx = ctx;
@@ -258,17 +294,21 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     refs->R_L = R_L;
     refs->R_U = R_U;
     hipError_t e = hipSuccess;
-    if (R_L > 0) {
-        e = hipMalloc(&refs->d_lower_nbits, sizeof(uint32_t) * lo.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(refs->d_lower_nbits, lo.data(), sizeof(uint32_t) * lo.size(),
-                          hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && R_U > 0) {
-        e = hipMalloc(&refs->d_upper_bits, sizeof(uint32_t) * up.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(refs->d_upper_bits, up.data(), sizeof(uint32_t) * up.size(),
-                          hipMemcpyHostToDevice);
+    auto upload = [&](void** dst, const void* src, size_t bytes) {
+        if (e != hipSuccess || bytes == 0) return;
+        e = hipMalloc(dst, bytes);
+        if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    upload(reinterpret_cast<void**>(&refs->d_lower_nbits), lo.data(), sizeof(uint32_t) * lo.size());
+    upload(reinterpret_cast<void**>(&refs->d_upper_bits), up.data(), sizeof(uint32_t) * up.size());
+    if (with_mfma) {
+        refs->KS = KS;
+        refs->TL = TL;
+        refs->TU = TU;
+        upload(reinterpret_cast<void**>(&refs->d_lower_frag), lof.data(), lof.size());
+        upload(reinterpret_cast<void**>(&refs->d_lower_cinit), loc.data(), sizeof(int32_t) * loc.size());
+        upload(reinterpret_cast<void**>(&refs->d_upper_frag), upf.data(), upf.size());
+        upload(reinterpret_cast<void**>(&refs->d_upper_cinit), upc.data(), sizeof(int32_t) * upc.size());
     }
     if (e != hipSuccess) {
         rsr_refs_destroy(refs);
@@ -283,8 +323,10 @@ rsr_status rsr_refs_destroy(rsr_refs* refs) {
     DeviceGuard g(refs->ctx->device);
     if (refs->d_lower_nbits) (void)hipFree(refs->d_lower_nbits);
     if (refs->d_upper_bits) (void)hipFree(refs->d_upper_bits);
-    if (refs->d_lower_i8) (void)hipFree(refs->d_lower_i8);
-    if (refs->d_upper_i8) (void)hipFree(refs->d_upper_i8);
+    if (refs->d_lower_frag) (void)hipFree(refs->d_lower_frag);
+    if (refs->d_lower_cinit) (void)hipFree(refs->d_lower_cinit);
+    if (refs->d_upper_frag) (void)hipFree(refs->d_upper_frag);
+    if (refs->d_upper_cinit) (void)hipFree(refs->d_upper_cinit);
     delete refs;
     return RSR_OK;
 }
@@ -362,11 +404,13 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         return fail(ctx, RSR_EINVAL, "bad form");
     if (refs->ctx->device != ctx->device) return fail(ctx, RSR_EINVAL, "refs on another device");
     DeviceGuard g(ctx->device);
-    if (form == RSR_MFMA) {
-        return fail(ctx, RSR_EUNSUPPORTED, "MFMA form not built");
-    }
-    RSR_HIP(ctx, rsr::launch_dom_bits(ctx->stream, refs, d_samples, N, mode, d_flags,
-                                      mode == RSR_COUNT ? d_match : nullptr));
+    if (form == RSR_MFMA && refs->KS == 0)
+        return fail(ctx, RSR_EUNSUPPORTED, "matrix-core form needs n*(K-1) <= 1280");
+    uint32_t* match = mode == RSR_COUNT ? d_match : nullptr;
+    if (form == RSR_MFMA)
+        RSR_HIP(ctx, rsr::launch_dom_mfma(ctx->stream, refs, d_samples, N, mode, d_flags, match));
+    else
+        RSR_HIP(ctx, rsr::launch_dom_bits(ctx->stream, refs, d_samples, N, mode, d_flags, match));
     return RSR_OK;
 }
 
@@ -398,8 +442,8 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
     if (!d_flags || !out) return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
     DeviceGuard g(ctx->device);
-    RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, ctx->ws.counters, 5, 0));
-    RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters));
+    RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
+                                    ctx->ws.count_part));
     RSR_HIP(ctx, hipMemcpyAsync(ctx->ws.host_counts, ctx->ws.counters, sizeof(uint64_t) * 5,
                                 hipMemcpyDeviceToHost, ctx->stream));
     RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -431,9 +475,7 @@ rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samp
     if (!model || !d_samples || !d_Y || !d_G) return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
     DeviceGuard g(ctx->device);
-    const int W = sample_words(model->n, model->K);
-    RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, ctx->ws.grad_acc, W * 32 + 1, 0));
-    RSR_HIP(ctx, rsr::launch_grad(ctx->stream, model, d_samples, d_Y, N, ctx->ws.grad_acc, d_G,
+    RSR_HIP(ctx, rsr::launch_grad(ctx->stream, model, d_samples, d_Y, N, ctx->ws.grad_part, d_G,
                                   d_counts));
     return RSR_OK;
 }

@@ -18,12 +18,19 @@ inline int sample_words(int n, int K) { return (K - 1) * plane_words(n); }
 // kernel instantiated for W words (>= W; pad words are zero).
 int dom_row_words(int W);
 
+// Reduction shapes (k_reduce.hip): at most this many blocks write partials.
+constexpr int kMaxReduceBlocks = 1024;
+constexpr int kMaxGradBlocks = 64;
+// Largest k-step count of the matrix-core form (n (K-1) <= 1280 bits).
+constexpr int kMaxMfmaSteps = 20;
+
 struct Workspace {
-    uint64_t* counters = nullptr;   // 16 u64 device counters
-    int32_t* list = nullptr;        // unknown-sample index list
+    uint64_t* counters = nullptr;      // 16 u64 device counters
+    uint64_t* count_part = nullptr;    // [kMaxReduceBlocks][8] u64 partial counts
+    int32_t* list = nullptr;           // unknown-sample index list
     int64_t list_cap = 0;
-    uint64_t* grad_acc = nullptr;   // [RSR_MAX_BITS + 1] u64
-    uint64_t* host_counts = nullptr;  // pinned, 16 u64
+    uint32_t* grad_part = nullptr;     // [RSR_MAX_BITS * kMaxGradBlocks + kMaxGradBlocks] u32
+    uint64_t* host_counts = nullptr;   // pinned, 16 u64
 };
 
 }  // namespace rsr
@@ -49,10 +56,13 @@ struct rsr_refs {
     int64_t R_L = 0, R_U = 0;
     uint32_t* d_lower_nbits = nullptr;  // [R_L][WR]: NOT t(r), pad bits 0
     uint32_t* d_upper_bits = nullptr;   // [R_U][WR]: t(r)
-    int KP = 0;                          // int8 row length (multiple of 64)
-    int8_t* d_lower_i8 = nullptr;        // [R_Lp][KP]: NOT t(r) as 0/1 bytes
-    int8_t* d_upper_i8 = nullptr;        // [R_Up][KP]: t(r) as 0/1 bytes
-    int64_t R_Lp = 0, R_Up = 0;          // row counts padded for the MFMA tiles
+    // Matrix-core operands (k_dom_mfma.hip); absent when KS > kMaxMfmaSteps.
+    int KS = 0;                          // 64-wide k-steps: ceil(32 W / 64)
+    int TL = 0, TU = 0;                  // 16-row tiles per side
+    int8_t* d_lower_frag = nullptr;      // [TL][KS][64 lanes][16]: NOT t(r) as 0/1 bytes
+    int32_t* d_lower_cinit = nullptr;    // [TL * 16]: 0 (row) or 1 (pad row)
+    int8_t* d_upper_frag = nullptr;      // [TU][KS][64][16]: t(r) as 0/1 bytes
+    int32_t* d_upper_cinit = nullptr;    // [TU * 16]: -|t(r)| (row) or 1 (pad row)
 };
 
 struct rsr_system {
@@ -69,8 +79,7 @@ hipError_t launch_sample(hipStream_t st, const rsr_model* m, uint64_t seed, uint
 hipError_t launch_dom_bits(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
                            int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match);
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
-                           int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match,
-                           int32_t* d_acc);
+                           int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match);
 hipError_t launch_label(hipStream_t st, const uint8_t* d_flags, int64_t N, int which,
                         uint8_t* d_Y, int32_t* d_list, uint64_t* d_counter);
 hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const uint32_t* d_samples,
@@ -78,9 +87,9 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const uint32_t* d_s
                       uint8_t* d_Y, uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
 hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
-                         uint64_t* d_counters);
+                         uint64_t* d_counters, uint64_t* d_partial);
 hipError_t launch_grad(hipStream_t st, const rsr_model* m, const uint32_t* d_samples,
-                       const uint8_t* d_Y, int64_t N, uint64_t* d_acc, float* d_G,
+                       const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
                        uint64_t* d_counts);
 hipError_t launch_copy_u64(hipStream_t st, const uint64_t* src, uint64_t* dst, int count);
 

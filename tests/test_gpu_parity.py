@@ -57,33 +57,42 @@ def test_sample_bit_identical(rsr_ctx, n, K, N, first, stream):
 
 # ------------------------------------------------------------- classifier ----
 
+FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA)
+
+
 def _classify_both(ctx, cfg, N, lower, upper, level=1):
+    """Both kernel forms in both modes; returns {form: (label flags, count
+    flags, match counts)} and the oracle's answers."""
     n, K = cfg["n"], cfg["K"]
     p = cfg["p"]
     m, xs = _sample(ctx, p, cfg["seed"], cfg["stream"], 0, N)
     refs = R.Refs(ctx, n, K, lower, upper)
-    fl = R.rsr_classify(ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT)
-    fc, mt = R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, R.RSR_POPCOUNT, want_match=True)
+    got = {}
+    for form in FORMS:
+        fl = R.rsr_classify(ctx, refs, xs, N, R.RSR_LABEL, form)
+        fc, mt = R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, form, want_match=True)
+        got[form] = (_np(fl), _np(fc), _np(mt).view(np.uint32))
     x = oracle.sample(p, cfg["seed"], cfg["stream"], 0, N)
     ol, _, _ = oracle.classify(lower, upper, x, mode=0)
     oc, mL, mU = oracle.classify(lower, upper, x, mode=1)
-    return (_np(fl), _np(fc), _np(mt).view(np.uint32)), (ol, oc, mL, mU), (m, xs, refs, x)
+    return got, (ol, oc, mL, mU), (m, xs, refs, x)
 
 
 def _assert_classify(got, want):
-    fl, fc, mt = got
     ol, oc, mL, mU = want
-    np.testing.assert_array_equal(fl, ol)
-    np.testing.assert_array_equal(fc, oc)
-    np.testing.assert_array_equal(mt[:, 0], mL)
-    np.testing.assert_array_equal(mt[:, 1], mU)
+    for form, (fl, fc, mt) in got.items():
+        np.testing.assert_array_equal(fl, ol, err_msg=f"label flags, form {form}")
+        np.testing.assert_array_equal(fc, oc, err_msg=f"count flags, form {form}")
+        np.testing.assert_array_equal(mt[:, 0], mL, err_msg=f"lower matches, form {form}")
+        np.testing.assert_array_equal(mt[:, 1], mU, err_msg=f"upper matches, form {form}")
 
 
 def test_classify_tiny_complete_refs(rsr_ctx):
     cfg = WL.configs.tiny(N=100_000)
     got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], cfg["lower"], cfg["upper"])
     _assert_classify(got, want)
-    assert int((got[0] & 3 == 0).sum()) == 0   # complete reference sets leave nothing unclassified
+    # complete reference sets leave nothing unclassified
+    assert int((got[R.RSR_POPCOUNT][0] & 3 == 0).sum()) == 0
 
 
 def test_classify_graph2_subset(rsr_ctx):
@@ -138,13 +147,13 @@ def test_classify_edge_shapes(rsr_ctx, RL, RU, N):
 
 # ---------------------------------------------------- eval / estimate / grad --
 
-def _full_path(ctx, cfg, N, lower, upper, level=1):
+def _full_path(ctx, cfg, N, lower, upper, level=1, form=R.RSR_POPCOUNT):
     n, K = cfg["n"], cfg["K"]
     g = cfg["graph"]
     m = R.Model(ctx, cfg["p"])
     refs = R.Refs(ctx, n, K, lower, upper)
     sysm = R.System(ctx, g, K=K, level=level)
-    est, buf = R.stage2(ctx, m, refs, sysm, N, cfg["seed"], stream_id=cfg["stream"])
+    est, buf = R.stage2(ctx, m, refs, sysm, N, cfg["seed"], stream_id=cfg["stream"], form=form)
     Gc = R.rsr_grad(ctx, m, buf.samples, buf.Y, N, want_counts=True)
     return est, buf, Gc, (m, refs, sysm)
 
@@ -175,8 +184,9 @@ def _assert_grad(G, counts, c, Gref):
     assert np.all(G[~nz] == 0.0)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("name", ["tiny", "graph2"])
-def test_full_path_bit_exact(rsr_ctx, name):
+def test_full_path_bit_exact(rsr_ctx, name, form):
     if name == "tiny":
         cfg = WL.configs.tiny(N=100_000)
         lower, upper = cfg["lower"][:-4], cfg["upper"][:-20]   # partial refs -> unknowns
@@ -184,7 +194,7 @@ def test_full_path_bit_exact(rsr_ctx, name):
         cfg = WL.configs.graph2(N=50_000)
         lower, upper = cfg["lower"][:2000], cfg["upper"][:2000]
     N = cfg["N"]
-    est, buf, (G, counts), _ = _full_path(rsr_ctx, cfg, N, lower, upper)
+    est, buf, (G, counts), _ = _full_path(rsr_ctx, cfg, N, lower, upper, form=form)
     x, fl, Y, nev, cnt, oest, c, Gref = _oracle_path(cfg, N, lower, upper)
     np.testing.assert_array_equal(_np(buf.flags), fl)
     np.testing.assert_array_equal(_np(buf.Y), Y)
@@ -235,7 +245,8 @@ def test_estimate_bounds_only(rsr_ctx):
 
 # ------------------------------------------------ full-size sampled checks ----
 
-def test_graph2_full_size_sampled(rsr_ctx):
+@pytest.mark.parametrize("form", FORMS)
+def test_graph2_full_size_sampled(rsr_ctx, form):
     """The benchmark configuration (119 nodes / 295 edges, 1e4 + 1e4 rows,
     N = 1e6), checked on 3000 sampled indices one by one."""
     cfg = WL.configs.graph2()
@@ -243,7 +254,7 @@ def test_graph2_full_size_sampled(rsr_ctx):
     m = R.Model(rsr_ctx, cfg["p"])
     refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
     sysm = R.System(rsr_ctx, cfg["graph"])
-    est, buf = R.stage2(rsr_ctx, m, refs, sysm, N, cfg["seed"])
+    est, buf = R.stage2(rsr_ctx, m, refs, sysm, N, cfg["seed"], form=form)
     G, counts = R.rsr_grad(rsr_ctx, m, buf.samples, buf.Y, N, want_counts=True)
     rng = np.random.default_rng(123)
     idx = np.unique(np.concatenate([rng.integers(0, N, 3000), [0, N - 1]])).astype(np.uint64)
@@ -269,15 +280,16 @@ def test_graph2_full_size_sampled(rsr_ctx):
     assert np.all(G[~nz] == 0.0)
 
 
-def test_scaling_full_size_sampled_counts(rsr_ctx):
+@pytest.mark.parametrize("form", FORMS)
+def test_scaling_full_size_sampled_counts(rsr_ctx, form):
     """Kernel-only scaling workload (n = 295, 1e5 + 1e5 rows, N = 1e6) in
     COUNT mode, exact match counts on 300 sampled samples."""
     cfg = WL.configs.scaling()
     N = cfg["N"]
     m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, N)
     refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
-    fc, mt = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, R.RSR_POPCOUNT, want_match=True)
-    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT)
+    fc, mt = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, form, want_match=True)
+    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
     rng = np.random.default_rng(7)
     idx = np.unique(rng.integers(0, N, 300)).astype(np.uint64)
     x = oracle.sample_at(cfg["p"], cfg["seed"], 0, idx)
@@ -291,10 +303,11 @@ def test_scaling_full_size_sampled_counts(rsr_ctx):
     np.testing.assert_array_equal(_np(fl)[ii], ol)
 
 
-def test_classify_deterministic(rsr_ctx):
+def test_classify_forms_agree_and_deterministic(rsr_ctx):
     cfg = WL.configs.graph2(N=100_000)
     m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, cfg["N"])
     refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
-    a = _np(R.rsr_classify(rsr_ctx, refs, xs, cfg["N"]))
-    b = _np(R.rsr_classify(rsr_ctx, refs, xs, cfg["N"]))
-    np.testing.assert_array_equal(a, b)
+    runs = [_np(R.rsr_classify(rsr_ctx, refs, xs, cfg["N"], R.RSR_COUNT, f, want_match=True)[1])
+            for f in (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA, R.RSR_POPCOUNT)]
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r, runs[0])
