@@ -42,6 +42,11 @@ def main():
                     help="target duration of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", default="popcount", choices=["auto", "popcount", "mfma"])
+    ap.add_argument("--skip-legs", action="store_true",
+                    help="only the graph2 step (no scaling / multi-state / batched legs)")
+    ap.add_argument("--batched-scale", type=float, default=0.25,
+                    help="reference rows of the batched workload, as a fraction of its sizes")
+    ap.add_argument("--batched-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
@@ -138,6 +143,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, R_L + R_U, args.cpu_seconds)
+    extra = {}
+    if not args.skip_legs:
+        extra["scaling_count_mode"] = scaling_leg(ctx, reps)
+        extra["multi_state"] = multi_leg(ctx, reps)
+        extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps)
 
     out = {
         "metric": "dominance tests/s (samples x reference states), whole Stage-2 step",
@@ -178,8 +188,152 @@ def main():
             "multiple_of_exhaustive_roofline": (tests / (label_ms * 1e-3)) / (VALU_PEAK_OPS / W),
         },
         "cpu_baseline": cpu,
+        **extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def _event_ms(fn, reps):
+    import numpy as np
+    import torch
+    fn()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def scaling_leg(ctx, reps):
+    """Kernel-only workload (n = 295, 1e5 + 1e5 Bernoulli rows, N = 1e6), both
+    classification forms in COUNT mode (every test in full) against their
+    rooflines."""
+    import paper_2604_17066_amd as R
+    import workloads as WL
+    cfg = WL.configs.scaling()
+    N, n = cfg["N"], cfg["n"]
+    model = R.Model(ctx, cfg["p"])
+    refs = R.Refs(ctx, n, 2, cfg["lower"], cfg["upper"])
+    xs = R.rsr_sample(ctx, model, cfg["seed"], 0, 0, N)
+    flags = R.rsr_classify(ctx, refs, xs, N)
+    tests = float(N) * (refs.R_L + refs.R_U)
+    W = model.words
+    KP = 64 * ((32 * W + 63) // 64)
+    out = {"workload": "n=295, 1e5 upper Bernoulli(0.05) + 1e5 lower Bernoulli(0.9) rows, "
+                       "N=1e6, COUNT mode", "tests": tests}
+    for name, form, ops, peak in (("popcount", R.RSR_POPCOUNT, W, VALU_PEAK_OPS),
+                                  ("mfma", R.RSR_MFMA, 2 * KP, MFMA_I8_PEAK_OPS)):
+        ms = _event_ms(lambda: R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, form, flags=flags),
+                       reps)
+        ach = tests * ops / (ms * 1e-3)
+        out[name] = {"kernel_ms": ms, "tests_per_s": tests / (ms * 1e-3), "achieved_TOPs": ach / 1e12,
+                     "peak_TOPs": peak / 1e12, "frac": ach / peak, "ops_per_test": ops}
+        log(f"scaling COUNT {name}: {ms:.2f} ms, {ach / peak * 100:.1f}% of peak")
+    return out
+
+
+def multi_leg(ctx, reps):
+    """Three-state edges on graph2, bottleneck levels 1 and 2 (5e4 rows per
+    level), N = 1e6: P(S >= 1), P(S >= 2), the PMF by differences and the fp32
+    gradients, full path per level."""
+    import paper_2604_17066_amd as R
+    import workloads as WL
+    cfg = WL.configs.multi()
+    N, n, K = cfg["N"], cfg["n"], cfg["K"]
+    model = R.Model(ctx, cfg["p"])
+    buf = R.Buffers(ctx, n, K, N)
+    res = {}
+    levels = {}
+    for k in (1, 2):
+        lv = cfg["levels"][k]
+        refs = R.Refs(ctx, n, K, lv["lower"], lv["upper"])
+        system = R.System(ctx, cfg["graph"], K=K, level=k)
+        levels[k] = (refs, system)
+    def one_pass():
+        ests = {}
+        for k, (refs, system) in levels.items():
+            ests[k], _ = R.stage2(ctx, model, refs, system, N, cfg["seed"], buffers=buf)
+        return ests
+    ests = one_pass()
+    import time as _t
+    import torch
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(reps):
+        ests = one_pass()
+    torch.cuda.synchronize()
+    ms = (_t.perf_counter() - t0) * 1e3 / reps
+    P1, P2 = ests[1]["P"], ests[2]["P"]
+    res = {"workload": "graph2 with states {0,1,2}, levels 1 and 2, 5e4 rows per level, N=1e6",
+           "ms_both_levels": ms, "P_ge1": P1, "P_ge2": P2,
+           "pmf": [1.0 - P1, P1 - P2, P2], "p_u": [ests[1]["p_u"], ests[2]["p_u"]],
+           "tests_per_s": float(N) * sum(r.R_L + r.R_U for r, _ in levels.values()) / (ms * 1e-3)}
+    log(f"multi-state: {ms:.2f} ms for both levels, P(S>=1)={P1:.5f} P(S>=2)={P2:.5f}")
+    return res
+
+
+def batched_leg(ctx, ref_scale, reps):
+    """64 hazard scenarios x 8 graphs = 512 jobs at N = 2^18 (SE <= 1e-3 for any
+    P): the batched plan (one graph launch) against the plain form (the
+    library's calls job by job, with a host sync per job for its estimate)."""
+    import time as _t
+    import numpy as np
+    import torch
+    import paper_2604_17066_amd as R
+    import workloads as WL
+    N = 1 << 18
+    t0 = _t.time()
+    cfg = WL.configs.batched(n_scen=64, N=N, ref_scale=ref_scale)
+    log(f"batched workload built in {_t.time() - t0:.1f}s")
+    systems = []
+    for sd in cfg["systems"]:
+        systems.append((sd, R.Refs(ctx, sd["n"], 2, sd["lower"], sd["upper"]), R.System(ctx, sd["graph"])))
+    jobs = []
+    for jd in cfg["jobs"]:
+        sd, refs, system = systems[jd["system"]]
+        jobs.append({"model": R.Model(ctx, jd["p"]), "refs": refs, "system": system,
+                     "seed": jd["seed"], "N": N, "buffers": R.Buffers(ctx, sd["n"], 2, N)})
+
+    def plain():
+        out = []
+        for jb in jobs:
+            est, _ = R.stage2(ctx, jb["model"], jb["refs"], jb["system"], N, jb["seed"],
+                              form=R.RSR_POPCOUNT, buffers=jb["buffers"])
+            out.append(est)
+        return out
+
+    plain_est = plain()
+    torch.cuda.synchronize()
+    t1 = _t.perf_counter()
+    for _ in range(reps):
+        plain_est = plain()
+    torch.cuda.synchronize()
+    plain_ms = (_t.perf_counter() - t1) * 1e3 / reps
+    t2 = _t.time()
+    plan = R.Plan(ctx, jobs, tune=True)
+    create_s = _t.time() - t2
+    plan.run()
+    est, grads = plan.results()
+    torch.cuda.synchronize()
+    t3 = _t.perf_counter()
+    for _ in range(reps):
+        plan.run()
+        est, grads = plan.results()
+    batched_ms = (_t.perf_counter() - t3) * 1e3 / reps
+    same = all(a["P"] == b["P"] and a["n_u"] == b["n_u"] for a, b in zip(est, plain_est))
+    se = max(e["se"] for e in est)
+    total_tests = float(N) * sum(len(cfg["jobs"]) // len(systems) * (r.R_L + r.R_U)
+                                 for _, r, _ in systems)
+    log(f"batched: plain {plain_ms:.1f} ms, plan {batched_ms:.1f} ms "
+        f"({plain_ms / batched_ms:.2f}x), identical={same}, max SE {se:.2e}")
+    plan.close()
+    return {"workload": f"64 hazard scenarios x 8 graphs (50-500 nodes), {len(jobs)} jobs, N=2^18 each, "
+                        f"reference rows x{ref_scale} of 1e3..2e5 per graph; P_sys and gradient per job",
+            "plain_ms": plain_ms, "batched_ms": batched_ms, "speedup": plain_ms / batched_ms,
+            "plan_create_s": create_s, "identical_estimates": same, "max_se": se,
+            "nominal_tests_per_s_batched": total_tests / (batched_ms * 1e-3)}
 
 
 def cpu_baseline(cfg, R_total, seconds):

@@ -145,6 +145,13 @@ rsr_status rsr_model_destroy(rsr_model* model);
 rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower,
                            int64_t R_L, const uint8_t* upper, int64_t R_U, rsr_refs** out);
 rsr_status rsr_refs_destroy(rsr_refs* refs);
+/* *out = 1 when no upper row lies below a lower row (checked on the device
+ * at creation).  Then no sample can be dominated on both sides (valid
+ * reference sets always pass; section 2.2), and rsr_classify in RSR_LABEL mode
+ * stops at a sample's first match on either side.  Rows are kept in order of
+ * increasing size (fewest constrained components first); no result depends on
+ * the order. */
+rsr_status rsr_refs_consistent(const rsr_refs* refs, int32_t* out);
 
 /* System function handle: copies the graph to the device.  EINVAL on a node
  * id out of range, source == sink, or level outside 1..K-1. */

@@ -10,7 +10,7 @@ from ._abi import (  # noqa: F401
     RSR_POPCOUNT, RSR_MFMA, RSR_UNKNOWN_ONLY, RSR_ALL, RSRError, lib,
 )
 from .api import (  # noqa: F401
-    Context, Model, Refs, System, Buffers, alloc_samples, rsr_sample, rsr_classify,
+    Context, Model, Refs, System, Buffers, Plan, alloc_samples, rsr_sample, rsr_classify,
     rsr_eval_unknown, rsr_estimate, rsr_grad, stage2,
 )
 from .autograd import RSRProbability, rsr_probability  # noqa: F401

@@ -59,6 +59,7 @@ SIGNATURES = {
     "rsr_model_destroy": (ctypes.c_int, [_vp]),
     "rsr_refs_create": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp, _i64, _pp]),
     "rsr_refs_destroy": (ctypes.c_int, [_vp]),
+    "rsr_refs_consistent": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
     "rsr_system_create": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_system_desc), _pp]),
     "rsr_system_destroy": (ctypes.c_int, [_vp]),
     "rsr_sample": (ctypes.c_int, [_vp, _vp, _u64, _u32, _u64, _i64, _vp]),

@@ -82,6 +82,12 @@ class Model:
 class Refs:
     """rsr_refs: lower [R_L][n] and upper [R_U][n] uint8 reference states."""
 
+    @property
+    def consistent(self):
+        out = ctypes.c_int32(0)
+        self.ctx.check(A.lib().rsr_refs_consistent(self.h, ctypes.byref(out)))
+        return bool(out.value)
+
     def __init__(self, ctx, n, K, lower, upper):
         lower = np.ascontiguousarray(np.asarray(lower, dtype=np.uint8).reshape(-1, n))
         upper = np.ascontiguousarray(np.asarray(upper, dtype=np.uint8).reshape(-1, n))
@@ -213,3 +219,54 @@ def stage2(ctx, model, refs, system, N, seed, stream_id=0, first=0, form=A.RSR_A
         ctx.check(lib.rsr_grad(h, model.h, _ptr(b.samples), _ptr(b.Y), int(N), _ptr(b.G), None))
     est = rsr_estimate(ctx, b.flags, b.Y, N) if estimate else None
     return est, b
+
+
+class Plan:
+    """rsr_plan over a list of jobs.  Each job is a dict with keys model, refs,
+    system, seed, N, buffers (a Buffers) and optionally stream_id and grad
+    (default True: the job's gradient goes to buffers.G)."""
+
+    def __init__(self, ctx, jobs, tune=True):
+        self.ctx = ctx
+        self.jobs = list(jobs)
+        arr = (A.rsr_job * len(self.jobs))()
+        for k, jb in enumerate(self.jobs):
+            b = jb["buffers"]
+            arr[k] = A.rsr_job(jb["model"].h.value, jb["refs"].h.value, jb["system"].h.value,
+                               int(jb["seed"]), int(jb.get("stream_id", 0)), int(jb["N"]),
+                               b.samples.data_ptr(), b.flags.data_ptr(), b.Y.data_ptr(),
+                               b.G.data_ptr() if jb.get("grad", True) else None)
+        self._arr = arr
+        h = ctypes.c_void_p()
+        ctx.check(A.lib().rsr_plan_create(ctx.h, arr, len(self.jobs), 1 if tune else 0,
+                                          ctypes.byref(h)))
+        self.h = h
+
+    def run(self):
+        self.ctx.check(A.lib().rsr_plan_run(self.h))
+
+    def results(self, want_grad=True):
+        est = (A.rsr_estimate_t * len(self.jobs))()
+        sizes = [jb["model"].n * jb["model"].K for jb in self.jobs]
+        G = np.zeros(sum(sizes), dtype=np.float32) if want_grad else None
+        self.ctx.check(A.lib().rsr_plan_results(
+            self.h, est, G.ctypes.data_as(ctypes.c_void_p) if want_grad else None))
+        out = [e.as_dict() for e in est]
+        if not want_grad:
+            return out, None
+        grads, off = [], 0
+        for jb, sz in zip(self.jobs, sizes):
+            grads.append(G[off:off + sz].reshape(jb["model"].n, jb["model"].K).copy())
+            off += sz
+        return out, grads
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().rsr_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

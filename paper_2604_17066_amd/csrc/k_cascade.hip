@@ -1,0 +1,326 @@
+// LABEL-mode classification on a consistent reference set (no upper row lies
+// below a lower row; section 2.2 valid reference sets always are): no sample
+// can be dominated on both sides, so the first match on either side decides
+// the label of Algorithm 1 and a sample can stop there.
+//
+// Rows are stored by increasing size, so most samples match among the first
+// few rows.  The classification runs in rounds over row ranges
+// [0, first), [first, first*growth), ... of both sides at once:
+//
+//   round 0 (k_casc_fused, all samples, read where they are): each lane tests
+//     S samples against the round's rows of both sides, interleaved, and the
+//     wave leaves the round as soon as all its lanes have matched (vote every 8
+//     rows).  Matched samples get their flag; the others are copied (packed
+//     words and global index) to a compact buffer.
+//   later rounds: the undecided samples are few, so the round's rows are split
+//     into `chunks` contiguous ranges taken by different waves (k_casc_test,
+//     grid y = chunk) to keep the GPU busy; a chunk that finds a match ORs it
+//     into the sample's match word, and k_casc_resolve then writes flags and
+//     compacts the still undecided samples.  A round whose rows do not warrant
+//     a split runs k_casc_fused on the compact buffer instead.
+//   the last round flags every remaining sample as unclassified.
+//
+// Compaction reserves output slots with one atomic per block (wave ballots,
+// an LDS prefix over the block's waves), not per wave, so the counter is not
+// contended.
+#include "rsr_internal.h"
+
+namespace rsr {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxChunks = 64;
+
+// Reserves output slots for the carrying lanes of the whole block; every
+// thread of the block must call it.  Returns this lane's slot.
+__device__ __forceinline__ int64_t block_reserve(bool carry, unsigned long long* counter,
+                                                 int* s_counts, unsigned long long* s_base) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t mask = __ballot(carry);
+    if (lane == 0) s_counts[wave] = __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const int c = s_counts[w];
+            s_counts[w] = tot;
+            tot += c;
+        }
+        *s_base = tot ? atomicAdd(counter, static_cast<unsigned long long>(tot)) : 0ull;
+    }
+    __syncthreads();
+    const int64_t slot = static_cast<int64_t>(*s_base) + s_counts[wave] +
+                         __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    return slot;
+}
+
+// Tests S samples per lane against rows [l0, l1) (lower) and [u0, u1)
+// (upper), interleaved; returns the OR-accumulated violation minima.
+template <int W, int S>
+__device__ __forceinline__ void test_rows(const uint32_t (&x)[S][W], const uint32_t (&nx)[S][W],
+                                          const bool (&live)[S], const uint32_t* __restrict__ low_n,
+                                          int l0, int l1, const uint32_t* __restrict__ up_b,
+                                          int u0, int u1, uint32_t (&mnL)[S],
+                                          uint32_t (&mnU)[S]) {
+    const int nL = l1 - l0, nU = u1 - u0;
+    const int n_max = nL > nU ? nL : nU;
+    for (int r0 = 0; r0 < n_max; r0 += 8) {
+#pragma unroll
+        for (int r = r0; r < r0 + 8; ++r) {
+            if (r < nL) {
+                const uint32_t* row = low_n + static_cast<int64_t>(l0 + r) * W;
+                uint32_t rw[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) rw[w] = row[w];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    uint32_t t = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) t = (x[s][w] & rw[w]) | t;
+                    mnL[s] = min(mnL[s], t);
+                }
+            }
+            if (r < nU) {
+                const uint32_t* row = up_b + static_cast<int64_t>(u0 + r) * W;
+                uint32_t rw[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) rw[w] = row[w];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    uint32_t t = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) t = (nx[s][w] & rw[w]) | t;
+                    mnU[s] = min(mnU[s], t);
+                }
+            }
+        }
+        bool done = true;
+#pragma unroll
+        for (int s = 0; s < S; ++s) done = done && (!live[s] || mnL[s] == 0u || mnU[s] == 0u);
+        if (__all(done)) break;
+    }
+}
+
+template <int W, int S>
+__global__ __launch_bounds__(kBlock) void k_casc_fused(
+    SegSrc seg, const uint32_t* __restrict__ csrc, int64_t cstride,
+    const int32_t* __restrict__ src_idx, const unsigned long long* __restrict__ src_count,
+    int w_real, const uint32_t* __restrict__ low_n, int l0, int l1,
+    const uint32_t* __restrict__ up_b, int u0, int u1, uint32_t* __restrict__ dst,
+    int32_t* __restrict__ dst_idx, uint32_t* __restrict__ dst_match, int64_t dst_stride,
+    unsigned long long* __restrict__ dst_count, int last) {
+    __shared__ int s_counts[kWaves];
+    __shared__ unsigned long long s_base;
+    const int64_t total = src_idx ? static_cast<int64_t>(*src_count) : seg.total;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // Block-uniform loop (block_reserve synchronises the block).
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBlock * S; b0 < total;
+         b0 += static_cast<int64_t>(gridDim.x) * kBlock * S) {
+        const int64_t j0 = b0 + static_cast<int64_t>(wave) * 64 * S;
+        uint32_t x[S][W], nx[S][W];
+        bool valid[S];
+        int64_t jj[S], gg[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            jj[s] = j0 + s * 64 + lane;
+            valid[s] = jj[s] < total;
+            gg[s] = valid[s] ? (src_idx ? static_cast<int64_t>(src_idx[jj[s]]) : jj[s]) : 0;
+            const uint32_t* base = csrc;
+            int64_t stride = cstride, at = jj[s];
+            if (!src_idx && valid[s]) {
+                int job;
+                seg_locate(seg, gg[s], job, at);
+                base = seg_words(seg, job, stride);
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                x[s][w] = (valid[s] && w < w_real) ? base[w * stride + at] : 0u;
+                nx[s][w] = ~x[s][w];
+            }
+        }
+        uint32_t mnL[S], mnU[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
+        if (__any(valid[0])) test_rows<W, S>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bool hit = mnL[s] == 0u || mnU[s] == 0u;
+            if (valid[s] && (hit || last)) {
+                int job;
+                int64_t h;
+                seg_locate(seg, gg[s], job, h);
+                seg_flags(seg, job)[h] =
+                    static_cast<uint8_t>(mnL[s] == 0u ? 1 : (mnU[s] == 0u ? 2 : 0));
+            }
+            if (last) continue;
+            const bool carry = valid[s] && !hit;
+            const int64_t d = block_reserve(carry, dst_count, s_counts, &s_base);
+            if (carry) {
+                dst_idx[d] = static_cast<int32_t>(gg[s]);
+                dst_match[d] = 0u;
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (w < w_real) dst[w * dst_stride + d] = x[s][w];
+            }
+        }
+    }
+}
+
+// One chunk of a split round: rows of chunk blockIdx.y for the compacted
+// samples; matches are ORed into match[d] (bit0 lower, bit1 upper).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_casc_test(
+    const uint32_t* __restrict__ csrc, int64_t cstride, const unsigned long long* __restrict__ src_count,
+    int w_real, const uint32_t* __restrict__ low_n, int l0, int l1,
+    const uint32_t* __restrict__ up_b, int u0, int u1, uint32_t* __restrict__ match) {
+    const int64_t total = static_cast<int64_t>(*src_count);
+    const int chunks = gridDim.y, c = blockIdx.y;
+    const int nL = l1 - l0, nU = u1 - u0;
+    const int cl0 = l0 + static_cast<int>((static_cast<int64_t>(nL) * c) / chunks);
+    const int cl1 = l0 + static_cast<int>((static_cast<int64_t>(nL) * (c + 1)) / chunks);
+    const int cu0 = u0 + static_cast<int>((static_cast<int64_t>(nU) * c) / chunks);
+    const int cu1 = u0 + static_cast<int>((static_cast<int64_t>(nU) * (c + 1)) / chunks);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t wave_stride = static_cast<int64_t>(gridDim.x) * kWaves;
+    for (int64_t j0 = wave_id * 64; j0 < total; j0 += wave_stride * 64) {
+        const int64_t d = j0 + lane;
+        bool live[1];
+        live[0] = d < total && match[d] == 0u;
+        if (!__any(live[0])) continue;
+        uint32_t x[1][W], nx[1][W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            x[0][w] = (live[0] && w < w_real) ? csrc[w * cstride + d] : 0u;
+            nx[0][w] = ~x[0][w];
+        }
+        uint32_t mnL[1] = {0xFFFFFFFFu}, mnU[1] = {0xFFFFFFFFu};
+        test_rows<W, 1>(x, nx, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU);
+        const uint32_t bits = (mnL[0] == 0u ? 1u : 0u) | (mnU[0] == 0u ? 2u : 0u);
+        if (live[0] && bits) atomicOr(&match[d], bits);
+    }
+}
+
+// Flags the samples a split round decided and compacts the others.
+__global__ __launch_bounds__(kBlock) void k_casc_resolve(
+    SegSrc seg, const uint32_t* __restrict__ csrc, int64_t cstride,
+    const int32_t* __restrict__ src_idx, const unsigned long long* __restrict__ src_count,
+    int w_real, const uint32_t* __restrict__ match, uint32_t* __restrict__ dst,
+    int32_t* __restrict__ dst_idx, uint32_t* __restrict__ dst_match, int64_t dst_stride,
+    unsigned long long* __restrict__ dst_count, int last) {
+    __shared__ int s_counts[kWaves];
+    __shared__ unsigned long long s_base;
+    const int64_t total = static_cast<int64_t>(*src_count);
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBlock; b0 < total;
+         b0 += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t d = b0 + threadIdx.x;
+        const bool valid = d < total;
+        const uint32_t bits = valid ? match[d] : 0u;
+        const int64_t g = valid ? static_cast<int64_t>(src_idx[d]) : 0;
+        if (valid && (bits || last)) {
+            int job;
+            int64_t h;
+            seg_locate(seg, g, job, h);
+            seg_flags(seg, job)[h] = static_cast<uint8_t>((bits & 1u) ? 1 : ((bits & 2u) ? 2 : 0));
+        }
+        if (last) continue;
+        const bool carry = valid && bits == 0u;
+        const int64_t o = block_reserve(carry, dst_count, s_counts, &s_base);
+        if (carry) {
+            dst_idx[o] = static_cast<int32_t>(g);
+            dst_match[o] = 0u;
+            for (int w = 0; w < w_real; ++w) dst[w * dst_stride + o] = csrc[w * cstride + d];
+        }
+    }
+}
+
+template <int W>
+hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                     const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap) {
+    constexpr int S0 = W <= 16 ? 2 : 1;
+    const int64_t N = seg.total;
+    auto blocks_for = [&](int64_t per_block, int64_t cap) {
+        int64_t b = (N + per_block - 1) / per_block;
+        if (b > cap) b = cap;
+        return b < 1 ? int64_t{1} : b;
+    };
+    const int n_max = static_cast<int>(refs->R_L > refs->R_U ? refs->R_L : refs->R_U);
+    int64_t lo = 0, hi = shape.first;
+    const uint32_t* csrc = nullptr;
+    const int32_t* src_idx = nullptr;
+    const uint32_t* src_match = nullptr;
+    const unsigned long long* src_count = nullptr;
+    for (int round = 0;; ++round) {
+        const bool last = hi >= n_max || round + 1 >= CascadeBuffers::kMaxRounds;
+        if (last) hi = n_max;
+        const int l0 = static_cast<int>(lo < refs->R_L ? lo : refs->R_L);
+        const int l1 = static_cast<int>(hi < refs->R_L ? hi : refs->R_L);
+        const int u0 = static_cast<int>(lo < refs->R_U ? lo : refs->R_U);
+        const int u1 = static_cast<int>(hi < refs->R_U ? hi : refs->R_U);
+        const int rows = (l1 - l0) > (u1 - u0) ? (l1 - l0) : (u1 - u0);
+        int chunks = round == 0 ? 1 : rows / (shape.split_rows > 0 ? shape.split_rows : 1 << 30);
+        if (chunks > kMaxChunks) chunks = kMaxChunks;
+        if (chunks < 1) chunks = 1;
+        uint32_t* dst = cb.words[round & 1];
+        int32_t* dst_idx = cb.index[round & 1];
+        uint32_t* dst_match = cb.match[round & 1];
+        unsigned long long* dst_count = reinterpret_cast<unsigned long long*>(cb.counters) + round;
+        hipError_t e;
+        if (chunks == 1) {
+            if (round == 0)
+                hipLaunchKernelGGL((k_casc_fused<W, S0>), dim3(static_cast<unsigned>(
+                                       blocks_for(static_cast<int64_t>(kBlock) * S0, grid_cap))),
+                                   dim3(kBlock), 0, st, seg, csrc, cb.stride, src_idx, src_count,
+                                   refs->W, refs->d_lower_nbits, l0, l1, refs->d_upper_bits, u0,
+                                   u1, dst, dst_idx, dst_match, cb.stride, dst_count, last ? 1 : 0);
+            else
+                hipLaunchKernelGGL((k_casc_fused<W, 1>), dim3(static_cast<unsigned>(
+                                       blocks_for(kBlock, grid_cap))),
+                                   dim3(kBlock), 0, st, seg, csrc, cb.stride, src_idx, src_count,
+                                   refs->W, refs->d_lower_nbits, l0, l1, refs->d_upper_bits, u0,
+                                   u1, dst, dst_idx, dst_match, cb.stride, dst_count, last ? 1 : 0);
+            e = hipGetLastError();
+        } else {
+            const int64_t bx = blocks_for(kBlock, grid_cap / chunks > 0 ? grid_cap / chunks : 1);
+            hipLaunchKernelGGL((k_casc_test<W>), dim3(static_cast<unsigned>(bx), chunks), dim3(kBlock),
+                               0, st, csrc, cb.stride, src_count, refs->W, refs->d_lower_nbits, l0,
+                               l1, refs->d_upper_bits, u0, u1, const_cast<uint32_t*>(src_match));
+            e = hipGetLastError();
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_casc_resolve, dim3(static_cast<unsigned>(blocks_for(kBlock, grid_cap))),
+                                   dim3(kBlock), 0, st, seg, csrc, cb.stride, src_idx, src_count,
+                                   refs->W, src_match, dst, dst_idx, dst_match, cb.stride, dst_count,
+                                   last ? 1 : 0);
+                e = hipGetLastError();
+            }
+        }
+        if (e != hipSuccess || last) return e;
+        csrc = dst;
+        src_idx = dst_idx;
+        src_match = dst_match;
+        src_count = dst_count;
+        lo = hi;
+        hi *= shape.growth;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_dom_cascade(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                              const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap) {
+    if (shape.first < 1 || shape.growth < 2) return hipErrorInvalidValue;
+    switch (refs->WR) {
+#define RSR_W_CASE(w) \
+    case w: return cascade_w<w>(st, refs, seg, cb, shape, grid_cap);
+        RSR_W_CASE(1) RSR_W_CASE(2) RSR_W_CASE(3) RSR_W_CASE(4) RSR_W_CASE(5) RSR_W_CASE(6)
+        RSR_W_CASE(8) RSR_W_CASE(10) RSR_W_CASE(12) RSR_W_CASE(16) RSR_W_CASE(20)
+        RSR_W_CASE(24) RSR_W_CASE(32) RSR_W_CASE(40) RSR_W_CASE(48) RSR_W_CASE(64)
+        RSR_W_CASE(96) RSR_W_CASE(128)
+#undef RSR_W_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rsr

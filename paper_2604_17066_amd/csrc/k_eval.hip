@@ -24,33 +24,40 @@ constexpr int kBfsBlock = 256;
 constexpr int kWavesPerBfsBlock = kBfsBlock / 64;
 constexpr int kMaxNodeWords = RSR_MAX_NODES / 32;
 
-__global__ __launch_bounds__(kLabelBlock) void k_label(const uint8_t* __restrict__ flags,
-                                                       int64_t N, uint8_t* __restrict__ Y,
-                                                       int32_t* __restrict__ list,
+__global__ __launch_bounds__(kLabelBlock) void k_label(SegSrc seg, int32_t* __restrict__ list,
                                                        unsigned long long* __restrict__ counter) {
-    const int64_t h = static_cast<int64_t>(blockIdx.x) * kLabelBlock + threadIdx.x;
-    const bool in = h < N;
-    const uint8_t f = in ? flags[h] : 1;
-    const bool unknown = (f & 3u) == 0u;
-    if (in) Y[h] = (f & 1u) ? 0 : ((f & 2u) ? 1 : 0);
-    const uint64_t mask = __ballot(unknown);
-    if (mask == 0) return;
     const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(mask)));
-    base = __shfl(base, leader);
-    if (unknown) {
-        const uint64_t below = mask & ((1ull << lane) - 1ull);
-        list[base + __popcll(below)] = static_cast<int32_t>(h);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kLabelBlock;
+    // Grid-stride over global indices; the loop bound is wave-uniform.
+    for (int64_t g0 = static_cast<int64_t>(blockIdx.x) * kLabelBlock + (threadIdx.x & ~63);
+         g0 < seg.total; g0 += stride) {
+        const int64_t g = g0 + lane;
+        const bool in = g < seg.total;
+        int job = 0;
+        int64_t h = 0;
+        if (in) seg_locate(seg, g, job, h);
+        const uint8_t f = in ? seg_flags(seg, job)[h] : 1;
+        const bool unknown = (f & 3u) == 0u;
+        if (in) seg_Y(seg, job)[h] = (f & 1u) ? 0 : ((f & 2u) ? 1 : 0);
+        const uint64_t mask = __ballot(unknown);
+        if (mask == 0) continue;
+        const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(mask)));
+        base = __shfl(base, leader);
+        if (unknown) {
+            const uint64_t below = mask & ((1ull << lane) - 1ull);
+            list[base + __popcll(below)] = static_cast<int32_t>(g);
+        }
     }
 }
 
 __global__ __launch_bounds__(kBfsBlock) void k_bfs(
-    const uint32_t* __restrict__ xs, int64_t N, int PW, int plane, const uint32_t* __restrict__ edges,
-    int n_edges, int n_nodes, int source, int sink, const int32_t* __restrict__ list,
-    const unsigned long long* __restrict__ count_ptr, int which, uint8_t* __restrict__ Y,
+    SegSrc seg, int PW, int plane, const uint32_t* __restrict__ edges, int n_edges, int n_nodes,
+    int source, int sink, const int32_t* __restrict__ list,
+    const unsigned long long* __restrict__ count_ptr, int which,
     unsigned long long* __restrict__ n_evaluated) {
+    const int64_t N = seg.total;
     __shared__ uint32_t s_edges[RSR_MAX_BITS];
     __shared__ uint32_t s_reach[kWavesPerBfsBlock][kMaxNodeWords];
 
@@ -71,13 +78,17 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBfsBlock;
 
     for (int64_t j = first + wave; j < total; j += stride) {
-        const int64_t h = which == RSR_ALL ? j : static_cast<int64_t>(list[j]);
+        const int64_t g = which == RSR_ALL ? j : static_cast<int64_t>(list[j]);
+        int job;
+        int64_t h, xstride;
+        seg_locate(seg, g, job, h);
+        const uint32_t* xs = seg_words(seg, job, xstride);
         // Usable-edge mask of this lane's edges.
         uint64_t usable = 0;
         for (int k = 0; k < edge_rounds; ++k) {
             const int e = lane + 64 * k;
             if (e < n_edges) {
-                const uint32_t word = xs[static_cast<int64_t>(plane * PW + (e >> 5)) * N + h];
+                const uint32_t word = xs[static_cast<int64_t>(plane * PW + (e >> 5)) * xstride + h];
                 usable |= static_cast<uint64_t>((word >> (e & 31)) & 1u) << k;
             }
         }
@@ -119,7 +130,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
             }
             if (!__any(changed)) break;
         }
-        if (lane == 0) Y[h] = static_cast<uint8_t>(result);
+        if (lane == 0) seg_Y(seg, job)[h] = static_cast<uint8_t>(result);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
@@ -127,25 +138,26 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
 
 }  // namespace
 
-hipError_t launch_label(hipStream_t st, const uint8_t* d_flags, int64_t N, int which,
-                        uint8_t* d_Y, int32_t* d_list, uint64_t* d_counter) {
-    (void)which;
-    const dim3 grid(static_cast<unsigned>((N + kLabelBlock - 1) / kLabelBlock));
-    hipLaunchKernelGGL(k_label, grid, dim3(kLabelBlock), 0, st, d_flags, N, d_Y, d_list,
-                       reinterpret_cast<unsigned long long*>(d_counter));
+hipError_t launch_label(hipStream_t st, const SegSrc& seg, int32_t* d_list, uint64_t* d_counter,
+                        int grid_cap) {
+    int64_t blocks = (seg.total + kLabelBlock - 1) / kLabelBlock;
+    if (blocks > grid_cap) blocks = grid_cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_label, dim3(static_cast<unsigned>(blocks)), dim3(kLabelBlock), 0, st, seg,
+                       d_list, reinterpret_cast<unsigned long long*>(d_counter));
     return hipGetLastError();
 }
 
-hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const uint32_t* d_samples, int64_t N,
-                      const int32_t* d_list, const uint64_t* d_count, int which, uint8_t* d_Y,
+hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
+                      const int32_t* d_list, const uint64_t* d_count, int which,
                       uint64_t* d_n_evaluated, int grid_blocks) {
-    const int64_t need = (N + kWavesPerBfsBlock - 1) / kWavesPerBfsBlock;
-    const int blocks = static_cast<int>(need < grid_blocks ? need : grid_blocks);
-    hipLaunchKernelGGL(k_bfs, dim3(blocks), dim3(kBfsBlock), 0, st, d_samples, N,
-                       plane_words(sys->n_edges), sys->level - 1, sys->d_edges, sys->n_edges,
-                       sys->n_nodes, sys->source, sys->sink, d_list,
-                       reinterpret_cast<const unsigned long long*>(d_count), which, d_Y,
-                       reinterpret_cast<unsigned long long*>(d_n_evaluated));
+    const int64_t need = (seg.total + kWavesPerBfsBlock - 1) / kWavesPerBfsBlock;
+    int blocks = static_cast<int>(need < grid_blocks ? need : grid_blocks);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_bfs, dim3(blocks), dim3(kBfsBlock), 0, st, seg, plane_words(sys->n_edges),
+                       sys->level - 1, sys->d_edges, sys->n_edges, sys->n_nodes, sys->source,
+                       sys->sink, d_list, reinterpret_cast<const unsigned long long*>(d_count),
+                       which, reinterpret_cast<unsigned long long*>(d_n_evaluated));
     return hipGetLastError();
 }
 

@@ -42,8 +42,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int6
 
 __global__ __launch_bounds__(kBlock) void k_counts(const uint8_t* __restrict__ flags,
                                                    const uint8_t* __restrict__ Y, int64_t N,
-                                                   unsigned long long* __restrict__ partial) {
-    // partial[block][0..4] = this block's n_L, n_U, n_u, n_both, n_u_up.
+                                                   unsigned long long* __restrict__ partial,
+                                                   const JobDev* __restrict__ jobs) {
+    // partial[job][block][0..4] = this block's n_L, n_U, n_u, n_both, n_u_up;
+    // with a job table, blockIdx.y selects the job.
+    if (jobs) {
+        const JobDev& jd = jobs[blockIdx.y];
+        flags = jd.flags;
+        Y = jd.Y;
+        N = jd.N;
+        partial += static_cast<int64_t>(blockIdx.y) * gridDim.x * 8;
+    }
     uint32_t nL = 0, nU = 0, nu = 0, nb = 0, nuu = 0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t h = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; h < N; h += stride) {
@@ -78,10 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_counts(const uint8_t* __restrict__ f
     }
 }
 
-// Sums the per-block partials of k_counts into out[0..4] (one block).
+// Sums the per-block partials of k_counts into out[0..4] (one block per job).
 __global__ __launch_bounds__(kBlock) void k_counts_final(const unsigned long long* __restrict__ partial,
                                                          int blocks,
                                                          unsigned long long* __restrict__ out) {
+    partial += static_cast<int64_t>(blockIdx.x) * blocks * 8;
+    out += static_cast<int64_t>(blockIdx.x) * 8;
     __shared__ unsigned long long red[kBlock / 64][5];
     unsigned long long v[5] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < blocks; b += kBlock)
@@ -105,7 +116,19 @@ __global__ __launch_bounds__(kBlock) void k_counts_final(const unsigned long lon
 __global__ __launch_bounds__(kBlock) void k_grad_bits(const uint32_t* __restrict__ xs,
                                                       const uint8_t* __restrict__ Y, int64_t N,
                                                       uint32_t* __restrict__ partial,
-                                                      uint32_t* __restrict__ ypart) {
+                                                      uint32_t* __restrict__ ypart,
+                                                      const JobDev* __restrict__ jobs,
+                                                      int64_t job_stride) {
+    // With a job table, blockIdx.z selects the job; its partials start at
+    // job * job_stride (u32).
+    if (jobs) {
+        const JobDev& jd = jobs[blockIdx.z];
+        xs = jd.samples;
+        Y = jd.Y;
+        N = jd.N;
+        partial += static_cast<int64_t>(blockIdx.z) * job_stride;
+        ypart += static_cast<int64_t>(blockIdx.z) * job_stride;
+    }
     const int w = blockIdx.y;
     uint32_t c[32];
 #pragma unroll
@@ -145,7 +168,19 @@ __global__ __launch_bounds__(kBlock) void k_grad_finalize(const uint32_t* __rest
                                                           int bx, const float* __restrict__ p,
                                                           int n, int K, int PW, int64_t N,
                                                           float* __restrict__ G,
-                                                          unsigned long long* __restrict__ counts) {
+                                                          unsigned long long* __restrict__ counts,
+                                                          const JobDev* __restrict__ jobs,
+                                                          int64_t job_stride) {
+    if (jobs) {
+        const JobDev& jd = jobs[blockIdx.y];
+        p = jd.p;
+        N = jd.N;
+        G = jd.G;
+        counts = nullptr;
+        partial += static_cast<int64_t>(blockIdx.y) * job_stride;
+        ypart += static_cast<int64_t>(blockIdx.y) * job_stride;
+        if (!G) return;
+    }
     const int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= n * K) return;
     const int i = idx / K, s = idx % K;
@@ -179,38 +214,47 @@ hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t 
 }
 
 hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
-                         uint64_t* d_counters, uint64_t* d_partial) {
+                         uint64_t* d_counters, uint64_t* d_partial, const JobDev* jobs,
+                         int n_jobs) {
     int64_t blocks = (N + kBlock * 16 - 1) / (kBlock * 16);
     if (blocks > kMaxReduceBlocks) blocks = kMaxReduceBlocks;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_counts, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, d_flags,
-                       d_Y, N, reinterpret_cast<unsigned long long*>(d_partial));
+    const int nj = jobs ? n_jobs : 1;
+    hipLaunchKernelGGL(k_counts, dim3(static_cast<unsigned>(blocks), nj), dim3(kBlock), 0, st,
+                       d_flags, d_Y, N, reinterpret_cast<unsigned long long*>(d_partial), jobs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_counts_final, dim3(1), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_counts_final, dim3(nj), dim3(kBlock), 0, st,
                        reinterpret_cast<const unsigned long long*>(d_partial),
                        static_cast<int>(blocks), reinterpret_cast<unsigned long long*>(d_counters));
     return hipGetLastError();
 }
 
-hipError_t launch_grad(hipStream_t st, const rsr_model* m, const uint32_t* d_samples,
-                       const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
-                       uint64_t* d_counts) {
-    const int PW = plane_words(m->n);
-    const int W = (m->K - 1) * PW;
+int64_t grad_blocks(int64_t N) {
     // About 64 samples per thread, at most kMaxGradBlocks blocks per word column.
     int64_t bx = (N + kBlock * 64 - 1) / (kBlock * 64);
     if (bx > kMaxGradBlocks) bx = kMaxGradBlocks;
     if (bx < 1) bx = 1;
+    return bx;
+}
+
+hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uint32_t* d_samples,
+                       const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
+                       uint64_t* d_counts, const JobDev* jobs, int n_jobs) {
+    const int PW = plane_words(n);
+    const int W = (K - 1) * PW;
+    const int64_t bx = grad_blocks(N);
+    const int64_t job_stride = static_cast<int64_t>(W) * bx * 32 + bx;
+    const int nj = jobs ? n_jobs : 1;
     uint32_t* ypart = d_partial + static_cast<int64_t>(W) * bx * 32;
-    hipLaunchKernelGGL(k_grad_bits, dim3(static_cast<unsigned>(bx), W), dim3(kBlock), 0, st,
-                       d_samples, d_Y, N, d_partial, ypart);
+    hipLaunchKernelGGL(k_grad_bits, dim3(static_cast<unsigned>(bx), W, nj), dim3(kBlock), 0, st,
+                       d_samples, d_Y, N, d_partial, ypart, jobs, job_stride);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int total = m->n * m->K;
-    hipLaunchKernelGGL(k_grad_finalize, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                       d_partial, ypart, static_cast<int>(bx), m->d_p, m->n, m->K, PW, N, d_G,
-                       reinterpret_cast<unsigned long long*>(d_counts));
+    const int total = n * K;
+    hipLaunchKernelGGL(k_grad_finalize, dim3((total + kBlock - 1) / kBlock, nj), dim3(kBlock), 0, st,
+                       d_partial, ypart, static_cast<int>(bx), d_p, n, K, PW, N, d_G,
+                       reinterpret_cast<unsigned long long*>(d_counts), jobs, job_stride);
     return hipGetLastError();
 }
 

@@ -35,15 +35,13 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     return {c0, c1, c2, c3};
 }
 
-// KM1 = K - 1 thermometer planes.
+// Draws sample index g (its Philox counter) and stores it as column h of the
+// word-major [W][N] array out.  KM1 = K - 1 thermometer planes.
 template <int KM1>
-__global__ __launch_bounds__(256) void k_sample(const uint64_t* __restrict__ thresh, int n,
-                                                int PW, uint32_t key0, uint32_t key1,
-                                                uint32_t stream_id, uint64_t first, int64_t N,
-                                                uint32_t* __restrict__ out) {
-    const int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (h >= N) return;
-    const uint64_t g = first + static_cast<uint64_t>(h);
+__device__ __forceinline__ void draw_sample(const uint64_t* __restrict__ thresh, int n, int PW,
+                                            uint32_t key0, uint32_t key1, uint32_t stream_id,
+                                            uint64_t g, int64_t h, int64_t N,
+                                            uint32_t* __restrict__ out) {
     const uint32_t glo = static_cast<uint32_t>(g), ghi = static_cast<uint32_t>(g >> 32);
     for (int wi = 0; wi < PW; ++wi) {
         uint32_t acc[KM1];
@@ -76,6 +74,41 @@ __global__ __launch_bounds__(256) void k_sample(const uint64_t* __restrict__ thr
 }
 
 template <int KM1>
+__global__ __launch_bounds__(256) void k_sample(const uint64_t* __restrict__ thresh, int n,
+                                                int PW, uint32_t key0, uint32_t key1,
+                                                uint32_t stream_id, uint64_t first, int64_t N,
+                                                uint32_t* __restrict__ out) {
+    const int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (h >= N) return;
+    draw_sample<KM1>(thresh, n, PW, key0, key1, stream_id, first + static_cast<uint64_t>(h), h,
+                     N, out);
+}
+
+// Every sample of every job of a plan segment (same n and K), grid-stride
+// over the segment's global index.
+template <int KM1>
+__global__ __launch_bounds__(256) void k_sample_jobs(const JobDev* __restrict__ jobs,
+                                                     const int64_t* __restrict__ offsets,
+                                                     int n_jobs, int64_t total, int n, int PW) {
+    SegSrc seg{};
+    seg.jobs = jobs;
+    seg.offsets = offsets;
+    seg.n_jobs = n_jobs;
+    seg.total = total;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += stride) {
+        int j;
+        int64_t h;
+        seg_locate(seg, g, j, h);
+        const JobDev& jd = jobs[j];
+        draw_sample<KM1>(jd.thresh, n, PW, static_cast<uint32_t>(jd.seed),
+                         static_cast<uint32_t>(jd.seed >> 32), jd.stream_id,
+                         static_cast<uint64_t>(h), h, jd.N, jd.samples);
+    }
+}
+
+template <int KM1>
 hipError_t launch_k(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t stream_id,
                     uint64_t first, int64_t N, uint32_t* d_samples) {
     const int threads = 256;
@@ -86,7 +119,31 @@ hipError_t launch_k(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t 
     return hipGetLastError();
 }
 
+template <int KM1>
+hipError_t launch_jobs_k(hipStream_t st, int n, const JobDev* jobs, const int64_t* offsets,
+                         int n_jobs, int64_t total, int grid_cap) {
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > grid_cap) blocks = grid_cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sample_jobs<KM1>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                       jobs, offsets, n_jobs, total, n, plane_words(n));
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_sample_jobs(hipStream_t st, int n, int K, const JobDev* jobs,
+                              const int64_t* offsets, int n_jobs, int64_t total, int grid_cap) {
+    switch (K - 1) {
+#define RSR_K_CASE(k) \
+    case k: return launch_jobs_k<k>(st, n, jobs, offsets, n_jobs, total, grid_cap);
+        RSR_K_CASE(1) RSR_K_CASE(2) RSR_K_CASE(3) RSR_K_CASE(4) RSR_K_CASE(5) RSR_K_CASE(6)
+        RSR_K_CASE(7) RSR_K_CASE(8) RSR_K_CASE(9) RSR_K_CASE(10) RSR_K_CASE(11) RSR_K_CASE(12)
+        RSR_K_CASE(13) RSR_K_CASE(14) RSR_K_CASE(15)
+#undef RSR_K_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_sample(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t stream_id,
                          uint64_t first, int64_t N, uint32_t* d_samples) {

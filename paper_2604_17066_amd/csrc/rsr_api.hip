@@ -3,6 +3,7 @@
 // packing, graph upload), workspace management and kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -98,6 +99,65 @@ rsr_status ensure_list(rsr_ctx* ctx, int64_t N) {
     return RSR_OK;
 }
 
+// A reference set is consistent when no upper row lies below a lower row:
+// then no sample can be dominated on both sides and the LABEL cascade may stop
+// at the first match.  Checked once on the device with the bit-packed kernel
+// itself (upper rows as samples against the lower rows).  Synchronous.
+rsr_status check_consistency(rsr_ctx* ctx, rsr_refs* refs, const std::vector<uint32_t>& up) {
+    refs->consistent = true;
+    if (refs->R_L == 0 || refs->R_U == 0) return RSR_OK;
+    const int64_t RU = refs->R_U;
+    const int W = refs->W, WR = refs->WR;
+    std::vector<uint32_t> cols(static_cast<size_t>(W) * RU);
+    for (int64_t r = 0; r < RU; ++r)
+        for (int w = 0; w < W; ++w) cols[static_cast<size_t>(w) * RU + r] = up[r * WR + w];
+    uint32_t* d_cols = nullptr;
+    uint8_t* d_flags = nullptr;
+    hipError_t e = hipMalloc(&d_cols, sizeof(uint32_t) * cols.size());
+    if (e == hipSuccess) e = hipMalloc(&d_flags, static_cast<size_t>(RU));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_cols, cols.data(), sizeof(uint32_t) * cols.size(),
+                           hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        rsr_refs lower_only = *refs;
+        lower_only.R_U = 0;
+        lower_only.d_upper_bits = nullptr;
+        e = rsr::launch_dom_bits(ctx->stream, &lower_only, d_cols, RU, RSR_LABEL, d_flags, nullptr);
+    }
+    std::vector<uint8_t> fl(static_cast<size_t>(RU));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(fl.data(), d_flags, fl.size(), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (d_cols) (void)hipFree(d_cols);
+    if (d_flags) (void)hipFree(d_flags);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reference consistency check");
+    for (uint8_t f : fl)
+        if (f & 1u) {
+            refs->consistent = false;
+            break;
+        }
+    return RSR_OK;
+}
+
+rsr_status ensure_cascade(rsr_ctx* ctx, int W, int64_t N) {
+    const int64_t words = 2 * static_cast<int64_t>(W) * N, idx = 4 * N;
+    if (ctx->ws.casc_words_cap < words) {
+        if (ctx->ws.casc_words) RSR_HIP(ctx, hipFree(ctx->ws.casc_words));
+        ctx->ws.casc_words = nullptr;
+        ctx->ws.casc_words_cap = 0;
+        RSR_HIP(ctx, hipMalloc(&ctx->ws.casc_words, sizeof(uint32_t) * static_cast<size_t>(words)));
+        ctx->ws.casc_words_cap = words;
+    }
+    if (ctx->ws.casc_index_cap < idx) {
+        if (ctx->ws.casc_index) RSR_HIP(ctx, hipFree(ctx->ws.casc_index));
+        ctx->ws.casc_index = nullptr;
+        ctx->ws.casc_index_cap = 0;
+        RSR_HIP(ctx, hipMalloc(&ctx->ws.casc_index, sizeof(int32_t) * static_cast<size_t>(idx)));
+        ctx->ws.casc_index_cap = idx;
+    }
+    return RSR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -147,6 +207,7 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
     ctx->cu_count = prop.multiProcessorCount;
     rsr_status st = RSR_OK;
     if (hipMalloc(&ctx->ws.counters, sizeof(uint64_t) * 16) != hipSuccess ||
+        hipMalloc(&ctx->ws.casc_counters, sizeof(uint64_t) * 16) != hipSuccess ||
         hipMalloc(&ctx->ws.count_part, sizeof(uint64_t) * rsr::kMaxReduceBlocks * 8) != hipSuccess ||
         hipMalloc(&ctx->ws.grad_part, sizeof(uint32_t) * (static_cast<size_t>(RSR_MAX_BITS) + 1) *
                                           rsr::kMaxGradBlocks) != hipSuccess ||
@@ -167,6 +228,9 @@ rsr_status rsr_ctx_destroy(rsr_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     if (ctx->ws.counters) (void)hipFree(ctx->ws.counters);
+    if (ctx->ws.casc_counters) (void)hipFree(ctx->ws.casc_counters);
+    if (ctx->ws.casc_words) (void)hipFree(ctx->ws.casc_words);
+    if (ctx->ws.casc_index) (void)hipFree(ctx->ws.casc_index);
     if (ctx->ws.list) (void)hipFree(ctx->ws.list);
     if (ctx->ws.count_part) (void)hipFree(ctx->ws.count_part);
     if (ctx->ws.grad_part) (void)hipFree(ctx->ws.grad_part);
@@ -250,6 +314,29 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     std::vector<uint32_t> lo(static_cast<size_t>(R_L) * WR), up(static_cast<size_t>(R_U) * WR);
     for (int64_t r = 0; r < R_L; ++r) pack(lower + r * n, lo.data() + r * WR, true);
     for (int64_t r = 0; r < R_U; ++r) pack(upper + r * n, up.data() + r * WR, false);
+    // Store rows by increasing number of violation bits (stable): a row with
+    // fewer constrained components dominates a larger region, so the LABEL
+    // cascade finds most matches among the first rows.  Results do not depend
+    // on the order.
+    auto sort_rows = [&](std::vector<uint32_t>& rows, int64_t R) {
+        std::vector<int64_t> order(R);
+        std::vector<int> weight(R);
+        for (int64_t r = 0; r < R; ++r) {
+            order[r] = r;
+            int c = 0;
+            for (int w = 0; w < W; ++w) c += __builtin_popcount(rows[r * WR + w]);
+            weight[r] = c;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t b) { return weight[a] < weight[b]; });
+        std::vector<uint32_t> sorted(rows.size());
+        for (int64_t r = 0; r < R; ++r)
+            std::copy(rows.begin() + order[r] * WR, rows.begin() + (order[r] + 1) * WR,
+                      sorted.begin() + r * WR);
+        rows.swap(sorted);
+    };
+    sort_rows(lo, R_L);
+    sort_rows(up, R_U);
 
     // Matrix-core operands: fragment-ordered 0/1 bytes and accumulator starts.
     const int KS = (W * 32 + 63) / 64;
@@ -314,7 +401,18 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
         rsr_refs_destroy(refs);
         return hip_fail(ctx, e, "rsr_refs_create upload");
     }
+    rsr_status st = check_consistency(ctx, refs, up);
+    if (st != RSR_OK) {
+        rsr_refs_destroy(refs);
+        return st;
+    }
     *out = refs;
+    return RSR_OK;
+}
+
+rsr_status rsr_refs_consistent(const rsr_refs* refs, int32_t* out) {
+    if (!refs || !out) return RSR_EINVAL;
+    *out = refs->consistent ? 1 : 0;
     return RSR_OK;
 }
 
@@ -407,6 +505,24 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
     if (form == RSR_MFMA && refs->KS == 0)
         return fail(ctx, RSR_EUNSUPPORTED, "matrix-core form needs n*(K-1) <= 1280");
     uint32_t* match = mode == RSR_COUNT ? d_match : nullptr;
+    if (mode == RSR_LABEL && form != RSR_MFMA && refs->consistent && N <= 0x7FFFFFFFll) {
+        rsr_status st = ensure_cascade(ctx, refs->W, N);
+        if (st != RSR_OK) return st;
+        rsr::CascadeBuffers cb;
+        cb.words[0] = ctx->ws.casc_words;
+        cb.words[1] = ctx->ws.casc_words + static_cast<int64_t>(refs->W) * N;
+        cb.index[0] = ctx->ws.casc_index;
+        cb.index[1] = ctx->ws.casc_index + N;
+        cb.match[0] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 2 * N);
+        cb.match[1] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 3 * N);
+        cb.stride = N;
+        cb.counters = ctx->ws.casc_counters;
+        RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0));
+        RSR_HIP(ctx, rsr::launch_dom_cascade(ctx->stream, refs,
+                                             rsr::single_src(d_samples, N, d_flags, nullptr), cb,
+                                             rsr::CascadeShape{}, ctx->cu_count * 8));
+        return RSR_OK;
+    }
     if (form == RSR_MFMA)
         RSR_HIP(ctx, rsr::launch_dom_mfma(ctx->stream, refs, d_samples, N, mode, d_flags, match));
     else
@@ -425,13 +541,14 @@ rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t*
         return fail(ctx, RSR_EINVAL, "d_flags is NULL with RSR_UNKNOWN_ONLY");
     DeviceGuard g(ctx->device);
     uint64_t* counter = ctx->ws.counters + 8;
+    const rsr::SegSrc seg = rsr::single_src(d_samples, N, const_cast<uint8_t*>(d_flags), d_Y);
     if (which == RSR_UNKNOWN_ONLY) {
         rsr_status st = ensure_list(ctx, N);
         if (st != RSR_OK) return st;
         RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, counter, 1, 0));
-        RSR_HIP(ctx, rsr::launch_label(ctx->stream, d_flags, N, which, d_Y, ctx->ws.list, counter));
+        RSR_HIP(ctx, rsr::launch_label(ctx->stream, seg, ctx->ws.list, counter, ctx->cu_count * 16));
     }
-    RSR_HIP(ctx, rsr::launch_bfs(ctx->stream, sys, d_samples, N, ctx->ws.list, counter, which, d_Y,
+    RSR_HIP(ctx, rsr::launch_bfs(ctx->stream, sys, seg, ctx->ws.list, counter, which,
                                  d_n_evaluated, ctx->cu_count * 8));
     return RSR_OK;
 }
@@ -475,27 +592,9 @@ rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samp
     if (!model || !d_samples || !d_Y || !d_G) return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
     DeviceGuard g(ctx->device);
-    RSR_HIP(ctx, rsr::launch_grad(ctx->stream, model, d_samples, d_Y, N, ctx->ws.grad_part, d_G,
-                                  d_counts));
+    RSR_HIP(ctx, rsr::launch_grad(ctx->stream, model->n, model->K, model->d_p, d_samples, d_Y, N,
+                                  ctx->ws.grad_part, d_G, d_counts));
     return RSR_OK;
 }
-
-// ---- batched plan (not yet built) ---------------------------------------------
-
-rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, int32_t tune,
-                           rsr_plan** out) {
-    (void)jobs;
-    (void)n_jobs;
-    (void)tune;
-    if (out) *out = nullptr;
-    return fail(ctx, RSR_EUNSUPPORTED, "batched plan not built");
-}
-rsr_status rsr_plan_run(rsr_plan* plan) { return plan ? RSR_EUNSUPPORTED : RSR_EINVAL; }
-rsr_status rsr_plan_results(rsr_plan* plan, rsr_estimate_t* est, float* G_host) {
-    (void)est;
-    (void)G_host;
-    return plan ? RSR_EUNSUPPORTED : RSR_EINVAL;
-}
-rsr_status rsr_plan_destroy(rsr_plan* plan) { return plan ? RSR_EUNSUPPORTED : RSR_EINVAL; }
 
 }  // extern "C"

@@ -31,6 +31,10 @@ struct Workspace {
     int64_t list_cap = 0;
     uint32_t* grad_part = nullptr;     // [RSR_MAX_BITS * kMaxGradBlocks + kMaxGradBlocks] u32
     uint64_t* host_counts = nullptr;   // pinned, 16 u64
+    uint64_t* casc_counters = nullptr; // [16] per-round cascade counters
+    uint32_t* casc_words = nullptr;    // 2 x [W][N] u32 (cascade)
+    int32_t* casc_index = nullptr;     // 2 x [N] i32 indices, then 2 x [N] u32 match words
+    int64_t casc_words_cap = 0, casc_index_cap = 0;
 };
 
 }  // namespace rsr
@@ -54,6 +58,7 @@ struct rsr_refs {
     rsr_ctx* ctx = nullptr;
     int n = 0, K = 0, W = 0, WR = 0;  // WR = packed row stride in words
     int64_t R_L = 0, R_U = 0;
+    bool consistent = false;            // no upper row lies below a lower row
     uint32_t* d_lower_nbits = nullptr;  // [R_L][WR]: NOT t(r), pad bits 0
     uint32_t* d_upper_bits = nullptr;   // [R_U][WR]: t(r)
     // Matrix-core operands (k_dom_mfma.hip); absent when KS > kMaxMfmaSteps.
@@ -73,24 +78,125 @@ struct rsr_system {
 
 namespace rsr {
 
+// Device-side record of one job of a batched plan.
+struct JobDev {
+    const uint64_t* thresh;  // [n][K-1]
+    const float* p;          // [n][K]
+    uint32_t* samples;       // [W][N]
+    uint8_t* flags;          // [N]
+    uint8_t* Y;              // [N]
+    float* G;                // [n][K] or nullptr
+    int64_t N;
+    uint64_t seed;
+    uint32_t stream_id;
+    int32_t n, K;
+};
+
+// Where a kernel finds its samples: one job (jobs == nullptr: samples / N /
+// flags / Y), or the jobs of a plan segment, addressed by a global index g in
+// [0, total) with offsets[j] = first g of job j.
+struct SegSrc {
+    const uint32_t* samples;
+    int64_t N;
+    uint8_t* flags;
+    uint8_t* Y;
+    const JobDev* jobs;
+    const int64_t* offsets;  // [n_jobs + 1]
+    int32_t n_jobs;
+    int64_t total;
+};
+
+inline SegSrc single_src(const uint32_t* samples, int64_t N, uint8_t* flags, uint8_t* Y) {
+    SegSrc s{};
+    s.samples = samples;
+    s.N = N;
+    s.flags = flags;
+    s.Y = Y;
+    s.total = N;
+    return s;
+}
+
+#ifdef __HIPCC__
+// Job j and sample h of global index g (binary search over the job offsets).
+__device__ __forceinline__ void seg_locate(const SegSrc& s, int64_t g, int& j, int64_t& h) {
+    if (!s.jobs) {
+        j = 0;
+        h = g;
+        return;
+    }
+    int lo = 0, hi = s.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.offsets[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    j = lo;
+    h = g - s.offsets[lo];
+}
+__device__ __forceinline__ const uint32_t* seg_words(const SegSrc& s, int j, int64_t& stride) {
+    if (!s.jobs) {
+        stride = s.N;
+        return s.samples;
+    }
+    stride = s.jobs[j].N;
+    return s.jobs[j].samples;
+}
+__device__ __forceinline__ uint8_t* seg_flags(const SegSrc& s, int j) {
+    return s.jobs ? s.jobs[j].flags : s.flags;
+}
+__device__ __forceinline__ uint8_t* seg_Y(const SegSrc& s, int j) {
+    return s.jobs ? s.jobs[j].Y : s.Y;
+}
+#endif
+
+// Ping-pong buffers of the LABEL-mode cascade (k_dom_cascade): compacted
+// sample words [W][N] and original indices [N], plus one counter per round.
+struct CascadeBuffers {
+    static constexpr int kMaxRounds = 12;
+    uint32_t* words[2] = {nullptr, nullptr};  // [W][stride] each
+    int32_t* index[2] = {nullptr, nullptr};   // [stride] each
+    uint32_t* match[2] = {nullptr, nullptr};  // [stride] each: match bits of split rounds
+    int64_t stride = 0;                       // capacity in samples (>= total)
+    uint64_t* counters = nullptr;  // [kMaxRounds], zeroed before the first round
+};
+
+// Round boundaries of the cascade: rows [0, first), [first, first*growth), ...
+// Rounds of more than split_rows rows (after round 0) are split into
+// rows / split_rows chunks taken by different waves.
+struct CascadeShape {
+    int first = 16;
+    int growth = 4;
+    int split_rows = 128;
+};
+
 // Kernel launchers (each returns the hipError_t of the launch).
 hipError_t launch_sample(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t stream_id,
                          uint64_t first, int64_t N, uint32_t* d_samples);
 hipError_t launch_dom_bits(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
                            int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match);
+hipError_t launch_dom_cascade(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                              const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap);
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
                            int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match);
-hipError_t launch_label(hipStream_t st, const uint8_t* d_flags, int64_t N, int which,
-                        uint8_t* d_Y, int32_t* d_list, uint64_t* d_counter);
-hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const uint32_t* d_samples,
-                      int64_t N, const int32_t* d_list, const uint64_t* d_count, int which,
-                      uint8_t* d_Y, uint64_t* d_n_evaluated, int grid_blocks);
+hipError_t launch_label(hipStream_t st, const SegSrc& seg, int32_t* d_list, uint64_t* d_counter,
+                        int grid_cap);
+hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
+                      const int32_t* d_list, const uint64_t* d_count, int which,
+                      uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
+// With a job table (jobs != nullptr) the reductions run once per job in one
+// launch; N must then be the largest job size (it sizes the grid), counters
+// receive [n_jobs][8] and the gradient partials need n_jobs * (W * bx * 32 +
+// bx) u32 with bx = grad_blocks(N).
 hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
-                         uint64_t* d_counters, uint64_t* d_partial);
-hipError_t launch_grad(hipStream_t st, const rsr_model* m, const uint32_t* d_samples,
+                         uint64_t* d_counters, uint64_t* d_partial, const JobDev* jobs = nullptr,
+                         int n_jobs = 1);
+int64_t grad_blocks(int64_t N);
+hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uint32_t* d_samples,
                        const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
-                       uint64_t* d_counts);
+                       uint64_t* d_counts, const JobDev* jobs = nullptr, int n_jobs = 1);
+hipError_t launch_sample_jobs(hipStream_t st, int n, int K, const JobDev* jobs,
+                              const int64_t* offsets, int n_jobs, int64_t total, int grid_cap);
 hipError_t launch_copy_u64(hipStream_t st, const uint64_t* src, uint64_t* dst, int count);
 
 }  // namespace rsr

@@ -1,0 +1,430 @@
+// Batched plan: many (model, reference set, system) jobs in one captured HIP
+// graph.
+//
+// Jobs that share a reference set and a system function form a segment
+// (reference states depend on the system only, not on the component
+// probabilities, section 5, so every hazard scenario of one network shares
+// them).  Each stage of the hot path runs once per segment over the
+// concatenation of its jobs' samples, addressed by a global index with a job
+// offset table: one sampler launch, one classification cascade, one label and
+// one BFS launch, one gradient and one count launch with a job grid dimension.
+// Small jobs therefore fill the GPU together and the launch count is
+// O(segments), not O(jobs).  Before capture an autotuner times the candidate
+// classification configurations of each segment on its own data and keeps the
+// fastest.  The whole plan, ending with the copy of every job's counts to
+// pinned host memory, is recorded into one HIP graph; rsr_plan_run is one
+// graph launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rsr_internal.h"
+
+namespace {
+
+enum Choice { kCascade = 0, kBitsPerJob = 1, kMfmaPerJob = 2 };
+
+struct Segment {
+    const rsr_refs* refs = nullptr;
+    const rsr_system* sys = nullptr;
+    int n = 0, K = 0, W = 0;
+    std::vector<int> jobs;  // plan job indices, in device order
+    int first_pos = 0;      // device position of the first job
+    int64_t total = 0, max_N = 0;
+    bool any_grad = false;
+    Choice choice = kCascade;
+    rsr::CascadeShape shape;
+    float tuned_ms = 0.0f;
+};
+
+}  // namespace
+
+struct rsr_plan {
+    rsr_ctx* ctx = nullptr;
+    std::vector<rsr_job> jobs;
+    std::vector<int> pos;  // plan job index -> device position
+    std::vector<Segment> segs;
+    rsr::JobDev* d_jobs = nullptr;
+    int64_t* d_offsets = nullptr;  // per segment [jobs + 1], concatenated
+    std::vector<int64_t> offset_base;
+    uint64_t* d_counts = nullptr;     // [jobs][8]
+    uint64_t* h_counts = nullptr;     // pinned [jobs][8]
+    uint64_t* d_count_part = nullptr;
+    uint32_t* d_grad_part = nullptr;
+    uint32_t* d_casc_words = nullptr;
+    int32_t* d_casc_index = nullptr;
+    int64_t casc_cap = 0;
+    int casc_w = 0;
+    uint64_t* d_casc_counters = nullptr;
+    int32_t* d_list = nullptr;
+    uint64_t* d_list_counter = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+rsr_status pfail(rsr_ctx* ctx, rsr_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+rsr_status phip(rsr_ctx* ctx, hipError_t e, const char* what) {
+    return pfail(ctx, e == hipErrorOutOfMemory ? RSR_ENOMEM : RSR_EHIP,
+                 std::string(what) + ": " + hipGetErrorName(e));
+}
+
+#define PLAN_HIP(ctx, call)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return phip(ctx, e_, #call);   \
+    } while (0)
+
+rsr::SegSrc seg_src(const rsr_plan* p, const Segment& s, int si) {
+    rsr::SegSrc src{};
+    src.jobs = p->d_jobs + s.first_pos;
+    src.offsets = p->d_offsets + p->offset_base[si];
+    src.n_jobs = static_cast<int32_t>(s.jobs.size());
+    src.total = s.total;
+    return src;
+}
+
+rsr::CascadeBuffers casc_buffers(const rsr_plan* p) {
+    rsr::CascadeBuffers cb;
+    cb.words[0] = p->d_casc_words;
+    cb.words[1] = p->d_casc_words + static_cast<int64_t>(p->casc_w) * p->casc_cap;
+    cb.index[0] = p->d_casc_index;
+    cb.index[1] = p->d_casc_index + p->casc_cap;
+    cb.match[0] = reinterpret_cast<uint32_t*>(p->d_casc_index + 2 * p->casc_cap);
+    cb.match[1] = reinterpret_cast<uint32_t*>(p->d_casc_index + 3 * p->casc_cap);
+    cb.stride = p->casc_cap;
+    cb.counters = p->d_casc_counters;
+    return cb;
+}
+
+hipError_t enqueue_sample(const rsr_plan* p, int si, hipStream_t st) {
+    const Segment& s = p->segs[si];
+    return rsr::launch_sample_jobs(st, s.n, s.K, p->d_jobs + s.first_pos,
+                                   p->d_offsets + p->offset_base[si],
+                                   static_cast<int>(s.jobs.size()), s.total, p->ctx->cu_count * 16);
+}
+
+hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice choice,
+                            const rsr::CascadeShape& shape) {
+    const Segment& s = p->segs[si];
+    if (choice == kCascade) {
+        const rsr::CascadeBuffers cb = casc_buffers(p);
+        hipError_t e = rsr::launch_fill_u64(st, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0);
+        if (e != hipSuccess) return e;
+        return rsr::launch_dom_cascade(st, s.refs, seg_src(p, s, si), cb, shape,
+                                       p->ctx->cu_count * 8);
+    }
+    for (int j : s.jobs) {
+        const rsr_job& jb = p->jobs[j];
+        hipError_t e = choice == kMfmaPerJob
+                           ? rsr::launch_dom_mfma(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
+                                                  jb.d_flags, nullptr)
+                           : rsr::launch_dom_bits(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
+                                                  jb.d_flags, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t enqueue_rest(const rsr_plan* p, int si, hipStream_t st) {
+    const Segment& s = p->segs[si];
+    const rsr::SegSrc src = seg_src(p, s, si);
+    const int nj = static_cast<int>(s.jobs.size());
+    hipError_t e = rsr::launch_fill_u64(st, p->d_list_counter, 1, 0);
+    if (e == hipSuccess)
+        e = rsr::launch_label(st, src, p->d_list, p->d_list_counter, p->ctx->cu_count * 16);
+    if (e == hipSuccess)
+        e = rsr::launch_bfs(st, s.sys, src, p->d_list, p->d_list_counter, RSR_UNKNOWN_ONLY, nullptr,
+                            p->ctx->cu_count * 8);
+    if (e == hipSuccess && s.any_grad)
+        e = rsr::launch_grad(st, s.n, s.K, nullptr, nullptr, nullptr, s.max_N, p->d_grad_part,
+                             nullptr, nullptr, p->d_jobs + s.first_pos, nj);
+    if (e == hipSuccess)
+        e = rsr::launch_counts(st, nullptr, nullptr, s.max_N,
+                               p->d_counts + static_cast<int64_t>(s.first_pos) * 8,
+                               p->d_count_part, p->d_jobs + s.first_pos, nj);
+    return e;
+}
+
+// Times each candidate classification of one segment on its own samples
+// (drawn once) and keeps the fastest.
+rsr_status tune_segment(rsr_plan* p, int si) {
+    Segment& s = p->segs[si];
+    rsr_ctx* ctx = p->ctx;
+    struct Cand {
+        Choice c;
+        rsr::CascadeShape shape;
+    };
+    std::vector<Cand> cands;
+    if (s.refs->consistent) {
+        const int firsts[] = {8, 16, 32, 64};
+        const int growths[] = {4, 8};
+        const int splits[] = {64, 256};
+        for (int f : firsts)
+            for (int g : growths)
+                for (int sp : splits) cands.push_back({kCascade, rsr::CascadeShape{f, g, sp}});
+    }
+    cands.push_back({kBitsPerJob, rsr::CascadeShape{}});
+    if (s.refs->KS > 0) cands.push_back({kMfmaPerJob, rsr::CascadeShape{}});
+    PLAN_HIP(ctx, enqueue_sample(p, si, p->cap));
+    hipEvent_t a, b;
+    PLAN_HIP(ctx, hipEventCreate(&a));
+    PLAN_HIP(ctx, hipEventCreate(&b));
+    float best = 1e30f;
+    for (const Cand& c : cands) {
+        PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));  // warm-up
+        PLAN_HIP(ctx, hipEventRecord(a, p->cap));
+        for (int rep = 0; rep < 2; ++rep) PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));
+        PLAN_HIP(ctx, hipEventRecord(b, p->cap));
+        PLAN_HIP(ctx, hipEventSynchronize(b));
+        float ms = 0.0f;
+        PLAN_HIP(ctx, hipEventElapsedTime(&ms, a, b));
+        if (ms < best) {
+            best = ms;
+            s.choice = c.c;
+            s.shape = c.shape;
+        }
+    }
+    s.tuned_ms = best / 2.0f;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return RSR_OK;
+}
+
+void free_plan(rsr_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    void* dev[] = {p->d_jobs, p->d_offsets, p->d_counts, p->d_count_part, p->d_grad_part,
+                   p->d_casc_words, p->d_casc_index, p->d_casc_counters, p->d_list,
+                   p->d_list_counter};
+    for (void* d : dev)
+        if (d) (void)hipFree(d);
+    if (p->h_counts) (void)hipHostFree(p->h_counts);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, int32_t tune,
+                           rsr_plan** out) {
+    if (!ctx || !out) return RSR_EINVAL;
+    *out = nullptr;
+    if (!jobs || n_jobs <= 0) return pfail(ctx, RSR_EINVAL, "no jobs");
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const rsr_job& jb = jobs[j];
+        if (!jb.model || !jb.refs || !jb.sys || !jb.d_samples || !jb.d_flags || !jb.d_Y)
+            return pfail(ctx, RSR_EINVAL, "job " + std::to_string(j) + ": NULL handle or buffer");
+        if (jb.N <= 0 || jb.N > 0x7FFFFFFFll)
+            return pfail(ctx, RSR_EINVAL, "job " + std::to_string(j) + ": N out of range");
+        if (jb.model->n != jb.refs->n || jb.model->K != jb.refs->K ||
+            jb.sys->n_edges != jb.refs->n || jb.sys->K != jb.refs->K)
+            return pfail(ctx, RSR_EINVAL, "job " + std::to_string(j) + ": n/K mismatch");
+        if (jb.model->ctx->device != ctx->device || jb.refs->ctx->device != ctx->device)
+            return pfail(ctx, RSR_EINVAL, "job " + std::to_string(j) + ": handle on another device");
+    }
+    rsr_plan* p = new (std::nothrow) rsr_plan();
+    if (!p) return pfail(ctx, RSR_ENOMEM, "host allocation");
+    p->ctx = ctx;
+    p->jobs.assign(jobs, jobs + n_jobs);
+    // Segments: jobs sharing (refs, system), in order of first appearance.
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const rsr_job& jb = jobs[j];
+        auto it = std::find_if(p->segs.begin(), p->segs.end(), [&](const Segment& s) {
+            return s.refs == jb.refs && s.sys == jb.sys;
+        });
+        if (it == p->segs.end()) {
+            Segment s;
+            s.refs = jb.refs;
+            s.sys = jb.sys;
+            s.n = jb.refs->n;
+            s.K = jb.refs->K;
+            s.W = jb.refs->W;
+            s.choice = jb.refs->consistent ? kCascade : kBitsPerJob;
+            p->segs.push_back(s);
+            it = p->segs.end() - 1;
+        }
+        it->jobs.push_back(j);
+        it->total += jb.N;
+        it->max_N = std::max(it->max_N, static_cast<int64_t>(jb.N));
+        it->any_grad = it->any_grad || jb.d_G != nullptr;
+    }
+    // Largest work first.
+    std::stable_sort(p->segs.begin(), p->segs.end(), [](const Segment& a, const Segment& b) {
+        return a.total * (a.W + a.refs->R_L + a.refs->R_U) >
+               b.total * (b.W + b.refs->R_L + b.refs->R_U);
+    });
+    p->pos.assign(n_jobs, 0);
+    std::vector<rsr::JobDev> host_jobs;
+    std::vector<int64_t> host_offsets;
+    int64_t max_total = 0, max_words = 0, max_grad = 0;
+    int max_jobs = 0;
+    for (Segment& s : p->segs) {
+        if (s.total > 0x7FFFFFFFll) {
+            free_plan(p);
+            return pfail(ctx, RSR_EUNSUPPORTED, "a segment holds more than 2^31-1 samples");
+        }
+        s.first_pos = static_cast<int>(host_jobs.size());
+        p->offset_base.push_back(static_cast<int64_t>(host_offsets.size()));
+        int64_t off = 0;
+        for (int j : s.jobs) {
+            const rsr_job& jb = jobs[j];
+            p->pos[j] = static_cast<int>(host_jobs.size());
+            rsr::JobDev d{};
+            d.thresh = jb.model->d_thresh;
+            d.p = jb.model->d_p;
+            d.samples = jb.d_samples;
+            d.flags = jb.d_flags;
+            d.Y = jb.d_Y;
+            d.G = jb.d_G;
+            d.N = jb.N;
+            d.seed = jb.seed;
+            d.stream_id = jb.stream_id;
+            d.n = s.n;
+            d.K = s.K;
+            host_jobs.push_back(d);
+            host_offsets.push_back(off);
+            off += jb.N;
+        }
+        host_offsets.push_back(off);
+        max_total = std::max(max_total, s.total);
+        max_words = std::max(max_words, static_cast<int64_t>(s.W));
+        max_jobs = std::max(max_jobs, static_cast<int>(s.jobs.size()));
+        const int64_t bx = rsr::grad_blocks(s.max_N);
+        max_grad = std::max(max_grad, static_cast<int64_t>(s.jobs.size()) *
+                                          (static_cast<int64_t>(s.W) * bx * 32 + bx));
+    }
+    p->casc_cap = max_total;
+    p->casc_w = static_cast<int>(max_words);
+    hipError_t e = hipSuccess;
+    auto dmalloc = [&](void** ptr, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(ptr, bytes > 0 ? bytes : 8);
+    };
+    dmalloc(reinterpret_cast<void**>(&p->d_jobs), sizeof(rsr::JobDev) * host_jobs.size());
+    dmalloc(reinterpret_cast<void**>(&p->d_offsets), sizeof(int64_t) * host_offsets.size());
+    dmalloc(reinterpret_cast<void**>(&p->d_counts), sizeof(uint64_t) * 8 * n_jobs);
+    dmalloc(reinterpret_cast<void**>(&p->d_count_part),
+            sizeof(uint64_t) * 8 * rsr::kMaxReduceBlocks * max_jobs);
+    dmalloc(reinterpret_cast<void**>(&p->d_grad_part), sizeof(uint32_t) * max_grad);
+    dmalloc(reinterpret_cast<void**>(&p->d_casc_words),
+            sizeof(uint32_t) * 2 * static_cast<size_t>(max_words) * max_total);
+    dmalloc(reinterpret_cast<void**>(&p->d_casc_index), sizeof(int32_t) * 4 * max_total);
+    dmalloc(reinterpret_cast<void**>(&p->d_casc_counters), sizeof(uint64_t) * 16);
+    dmalloc(reinterpret_cast<void**>(&p->d_list), sizeof(int32_t) * max_total);
+    dmalloc(reinterpret_cast<void**>(&p->d_list_counter), sizeof(uint64_t) * 2);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&p->h_counts), sizeof(uint64_t) * 8 * n_jobs,
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_jobs, host_jobs.data(), sizeof(rsr::JobDev) * host_jobs.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_offsets, host_offsets.data(), sizeof(int64_t) * host_offsets.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return phip(ctx, e, "rsr_plan_create allocation");
+    }
+    // Work enqueued on the context stream before this call must be finished
+    // before the tuner touches the jobs' buffers.
+    e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_plan(p);
+        return phip(ctx, e, "rsr_plan_create sync");
+    }
+    if (tune) {
+        for (size_t si = 0; si < p->segs.size(); ++si) {
+            rsr_status st = tune_segment(p, static_cast<int>(si));
+            if (st != RSR_OK) {
+                free_plan(p);
+                return st;
+            }
+        }
+    }
+    // Record the whole plan.
+    e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    for (size_t si = 0; si < p->segs.size() && e == hipSuccess; ++si) {
+        const Segment& s = p->segs[si];
+        e = enqueue_sample(p, static_cast<int>(si), p->cap);
+        if (e == hipSuccess) e = enqueue_classify(p, static_cast<int>(si), p->cap, s.choice, s.shape);
+        if (e == hipSuccess) e = enqueue_rest(p, static_cast<int>(si), p->cap);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_counts, p->d_counts, sizeof(uint64_t) * 8 * n_jobs,
+                           hipMemcpyDeviceToHost, p->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
+    if (e == hipSuccess) e = e2;
+    p->graph = graph;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return phip(ctx, e, "rsr_plan_create capture");
+    }
+    *out = p;
+    return RSR_OK;
+}
+
+rsr_status rsr_plan_run(rsr_plan* p) {
+    if (!p) return RSR_EINVAL;
+    PLAN_HIP(p->ctx, hipGraphLaunch(p->exec, p->ctx->stream));
+    return RSR_OK;
+}
+
+rsr_status rsr_plan_results(rsr_plan* p, rsr_estimate_t* est, float* G_host) {
+    if (!p) return RSR_EINVAL;
+    if (!est) return pfail(p->ctx, RSR_EINVAL, "NULL estimate array");
+    rsr_ctx* ctx = p->ctx;
+    PLAN_HIP(ctx, ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize());
+    size_t g_off = 0;
+    for (size_t j = 0; j < p->jobs.size(); ++j) {
+        const uint64_t* c = p->h_counts + static_cast<size_t>(p->pos[j]) * 8;
+        const rsr_job& jb = p->jobs[j];
+        rsr_estimate_t& o = est[j];
+        o.n_L = c[0];
+        o.n_U = c[1];
+        o.n_u = c[2];
+        o.n_both = c[3];
+        o.n_u_up = c[4];
+        o.N = static_cast<uint64_t>(jb.N);
+        const double Nd = static_cast<double>(jb.N);
+        o.p_L = static_cast<double>(o.n_L) / Nd;
+        o.p_U = static_cast<double>(o.n_U) / Nd;
+        o.p_u = static_cast<double>(o.n_u) / Nd;
+        const double P = static_cast<double>(o.n_U + o.n_u_up) / Nd;
+        o.P = P;
+        o.se = std::sqrt(P * (1.0 - P) / Nd);
+        o.cov = P > 0.0 ? std::sqrt((1.0 - P) / (Nd * P)) : HUGE_VAL;
+        const size_t gsz = static_cast<size_t>(jb.model->n) * jb.model->K;
+        if (G_host && jb.d_G)
+            PLAN_HIP(ctx, hipMemcpy(G_host + g_off, jb.d_G, sizeof(float) * gsz,
+                                    hipMemcpyDeviceToHost));
+        g_off += gsz;
+    }
+    return RSR_OK;
+}
+
+rsr_status rsr_plan_destroy(rsr_plan* p) {
+    if (!p) return RSR_EINVAL;
+    rsr_ctx* ctx = p->ctx;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    free_plan(p);
+    return RSR_OK;
+}
+
+}  // extern "C"

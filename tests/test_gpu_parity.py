@@ -87,6 +87,19 @@ def _assert_classify(got, want):
         np.testing.assert_array_equal(mt[:, 1], mU, err_msg=f"upper matches, form {form}")
 
 
+def test_refs_consistency_flag(rsr_ctx):
+    cfg = WL.configs.tiny(N=10)
+    assert R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"]).consistent
+    sc = WL.configs.scaling(N=10, R_U=200, R_L=200)
+    assert not R.Refs(rsr_ctx, sc["n"], 2, sc["lower"], sc["upper"]).consistent
+    n = 5
+    lower = np.array([[1, 1, 0, 1, 1]], dtype=np.uint8)
+    upper = np.array([[0, 1, 0, 0, 0], [0, 0, 1, 0, 0]], dtype=np.uint8)
+    assert not R.Refs(rsr_ctx, n, 2, lower, upper).consistent     # (0,1,0,0,0) <= lower row
+    assert R.Refs(rsr_ctx, n, 2, lower, upper[1:]).consistent
+    assert R.Refs(rsr_ctx, n, 2, lower[:0], upper).consistent
+
+
 def test_classify_tiny_complete_refs(rsr_ctx):
     cfg = WL.configs.tiny(N=100_000)
     got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], cfg["lower"], cfg["upper"])

@@ -1,0 +1,133 @@
+"""GPU tests of the batched plan: every job's flags, Y, counts, estimates and
+gradient must equal the plain one-job-at-a-time path bit for bit (and the
+oracle on a sampled job); graph replays must repeat exactly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_17066_amd as R
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _small_batch(ctx, n_scen=4, graphs=(0, 1, 2), Ns=(20_000, 12_345, 777, 3_001)):
+    cfg = WL.configs.batched(n_scen=n_scen, N=1, graphs=graphs, ref_scale=0.05)
+    systems = []
+    for sysd in cfg["systems"]:
+        refs = R.Refs(ctx, sysd["n"], 2, sysd["lower"], sysd["upper"])
+        system = R.System(ctx, sysd["graph"])
+        systems.append((sysd, refs, system))
+    jobs = []
+    for k, jd in enumerate(cfg["jobs"]):
+        sysd, refs, system = systems[jd["system"]]
+        N = Ns[k % len(Ns)]
+        jobs.append({"model": R.Model(ctx, jd["p"]), "refs": refs, "system": system,
+                     "seed": jd["seed"], "N": N, "grad": k % 3 != 2,
+                     "buffers": R.Buffers(ctx, sysd["n"], 2, N), "sys": sysd, "p": jd["p"]})
+    return jobs, systems
+
+
+def _plain(ctx, jb):
+    b = R.Buffers(ctx, jb["model"].n, 2, jb["N"])
+    est, b = R.stage2(ctx, jb["model"], jb["refs"], jb["system"], jb["N"], jb["seed"],
+                      form=R.RSR_POPCOUNT, buffers=b)
+    return est, b
+
+
+@pytest.mark.parametrize("tune", [False, True])
+def test_plan_equals_plain(rsr_ctx, tune):
+    jobs, systems = _small_batch(rsr_ctx)
+    plan = R.Plan(rsr_ctx, jobs, tune=tune)
+    plan.run()
+    est, grads = plan.results()
+    for k, jb in enumerate(jobs):
+        pe, pb = _plain(rsr_ctx, jb)
+        b = jb["buffers"]
+        np.testing.assert_array_equal(_np(b.samples), _np(pb.samples), err_msg=f"job {k}")
+        np.testing.assert_array_equal(_np(b.flags), _np(pb.flags), err_msg=f"job {k}")
+        np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k}")
+        for key, v in pe.items():
+            assert est[k][key] == v or (np.isinf(v) and np.isinf(est[k][key])), (k, key)
+        if jb["grad"]:
+            np.testing.assert_array_equal(grads[k], _np(pb.G), err_msg=f"job {k}")
+    plan.close()
+
+
+def test_plan_job_against_oracle(rsr_ctx):
+    jobs, _ = _small_batch(rsr_ctx, n_scen=2, graphs=(1,), Ns=(9_999,))
+    plan = R.Plan(rsr_ctx, jobs, tune=True)
+    plan.run()
+    est, grads = plan.results()
+    jb = jobs[1]
+    sysd = jb["sys"]
+    x = oracle.sample(jb["p"], jb["seed"], 0, 0, jb["N"])
+    fl, _, _ = oracle.classify(sysd["lower"], sysd["upper"], x, mode=0)
+    Y, _ = oracle.eval_unknown(sysd["graph"], x, fl)
+    cnt = oracle.counts(fl, Y)
+    oest = oracle.estimate(cnt)
+    np.testing.assert_array_equal(_np(jb["buffers"].flags), fl)
+    np.testing.assert_array_equal(_np(jb["buffers"].Y), Y)
+    assert est[1]["P"] == oest[3] and est[1]["n_u"] == int(cnt[2])
+    c, Gref = oracle.grad(jb["p"], x, Y)
+    nz = Gref != 0
+    assert np.max(np.abs(grads[1][nz] - Gref[nz]) / np.abs(Gref[nz])) <= 1e-5
+    plan.close()
+
+
+def test_plan_replays_identical(rsr_ctx):
+    jobs, _ = _small_batch(rsr_ctx, n_scen=3, graphs=(0, 2))
+    plan = R.Plan(rsr_ctx, jobs, tune=False)
+    ref = None
+    for rep in range(4):
+        plan.run()
+        est, grads = plan.results()
+        snap = ([dict(e) for e in est], [g.copy() for g in grads],
+                [_np(jb["buffers"].flags).copy() for jb in jobs])
+        # Eager work of the program between replays.
+        junk = torch.randn(1 << 16, device="cuda").sum().item()
+        assert np.isfinite(junk)
+        if ref is None:
+            ref = snap
+            continue
+        for a, b in zip(snap[0], ref[0]):
+            assert a == b or all(a[k] == b[k] or (np.isinf(a[k]) and np.isinf(b[k])) for k in a)
+        for a, b in zip(snap[1], ref[1]):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(snap[2], ref[2]):
+            np.testing.assert_array_equal(a, b)
+    plan.close()
+
+
+def test_plan_inconsistent_segment_uses_precedence(rsr_ctx):
+    """Rows that are not valid reference states (a lower row above an upper
+    row): the plan must keep Algorithm 1's lower precedence."""
+    cfg = WL.configs.tiny(N=10)
+    n = cfg["n"]
+    lower = WL.bernoulli_rows(40, n, 0.85, seed=1)
+    upper = WL.bernoulli_rows(30, n, 0.2, seed=2)
+    refs = R.Refs(rsr_ctx, n, 2, lower, upper)
+    assert not refs.consistent
+    system = R.System(rsr_ctx, cfg["graph"])
+    jobs = []
+    for k in range(3):
+        N = 5_000 + 17 * k
+        jobs.append({"model": R.Model(rsr_ctx, cfg["p"]), "refs": refs, "system": system,
+                     "seed": 50 + k, "N": N, "buffers": R.Buffers(rsr_ctx, n, 2, N)})
+    plan = R.Plan(rsr_ctx, jobs, tune=True)
+    plan.run()
+    est, _ = plan.results()
+    for k, jb in enumerate(jobs):
+        x = oracle.sample(cfg["p"], jb["seed"], 0, 0, jb["N"])
+        fl, _, _ = oracle.classify(lower, upper, x, mode=0)
+        np.testing.assert_array_equal(_np(jb["buffers"].flags), fl)
+        Y, _ = oracle.eval_unknown(cfg["graph"], x, fl)
+        cnt = oracle.counts(fl, Y)
+        assert est[k]["n_L"] == int(cnt[0]) and est[k]["n_u_up"] == int(cnt[4])
+    plan.close()

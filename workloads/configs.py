@@ -132,7 +132,7 @@ BATCH_REFS = (1_000, 2_100, 4_500, 9_700, 21_000, 44_000, 94_000, 200_000)
 
 @functools.lru_cache(maxsize=None)
 def _batch_graph(g_idx):
-    g = G.rgg(BATCH_NODES[g_idx], BATCH_EDGES[g_idx], seed=5 + g_idx)
+    g = G.rgg(BATCH_NODES[g_idx], BATCH_EDGES[g_idx], seed=5 + g_idx, spanning=True)
     s, t = G.st_degree_rule(g)
     return G.with_terminals(g, s, t)
 

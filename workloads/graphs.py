@@ -12,19 +12,47 @@ def _connected(n_nodes, eu, ev):
     return ncomp == 1
 
 
-def rgg(n_nodes: int, n_edges: int, seed: int, max_tries: int = 1000):
+def rgg(n_nodes: int, n_edges: int, seed: int, max_tries: int = 1000, spanning: bool = False):
     """Connected random geometric graph with exactly n_edges edges.
 
     Nodes are uniform in the unit square (PCG64 seeded with `seed`); the edges
     are the n_edges closest node pairs, ties broken by (distance, i, j).  A
-    disconnected draw is redrawn with seed+1, seed+2, ...  Edge e joins
-    edge_u[e] < edge_v[e]; edges are listed in order of increasing length."""
+    disconnected draw is redrawn with seed+1, seed+2, ...  With spanning=True
+    (for sizes where the closest pairs are rarely connected) the edges are
+    instead the Euclidean minimum spanning tree plus the closest remaining
+    pairs.  Edge e joins edge_u[e] < edge_v[e]; edges are listed in order of
+    increasing length."""
     for k in range(max_tries):
         rng = np.random.default_rng(seed + k)
         pos = rng.random((n_nodes, 2))
         iu, ju = np.triu_indices(n_nodes, k=1)
         d = np.hypot(pos[iu, 0] - pos[ju, 0], pos[iu, 1] - pos[ju, 1])
-        order = np.lexsort((ju, iu, d))[:n_edges]
+        ranked = np.lexsort((ju, iu, d))
+        if spanning:
+            # Kruskal over the ranked pairs, then fill with the shortest others.
+            parent = np.arange(n_nodes)
+
+            def find(x):
+                while parent[x] != x:
+                    parent[x] = parent[parent[x]]
+                    x = parent[x]
+                return x
+
+            tree = []
+            for r in ranked:
+                a, b = find(iu[r]), find(ju[r])
+                if a != b:
+                    parent[a] = b
+                    tree.append(r)
+                    if len(tree) == n_nodes - 1:
+                        break
+            in_tree = np.zeros(ranked.size, dtype=bool)
+            in_tree[tree] = True
+            rest = ranked[~in_tree[ranked]][: n_edges - len(tree)]
+            chosen = np.concatenate([np.array(tree, dtype=ranked.dtype), rest])
+            order = chosen[np.lexsort((ju[chosen], iu[chosen], d[chosen]))]
+        else:
+            order = ranked[:n_edges]
         eu = iu[order].astype(np.int32)
         ev = ju[order].astype(np.int32)
         if _connected(n_nodes, eu, ev):

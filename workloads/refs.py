@@ -54,6 +54,11 @@ def all_min_paths(graph, s=None, t=None):
     return sorted(set(out))
 
 
+def _csr_parts(graph):
+    eu, ev = graph["edge_u"], graph["edge_v"]
+    return np.concatenate([eu, ev]), np.concatenate([ev, eu])
+
+
 def _reach(adj, start, blocked):
     seen = {start}
     stack = [start]
@@ -93,9 +98,11 @@ def all_min_cuts(graph, s=None, t=None):
     return sorted(out)
 
 
-def sample_paths(graph, p_edge, count, seed, s=None, t=None, max_calls=None):
-    """Distinct probable s-t paths: shortest paths under the weights
-    -log(p_e) times independent Exp(1) noise (PCG64, `seed`)."""
+def sample_paths(graph, p_edge, count, seed, s=None, t=None, vias_per_draw=64, max_draws=None):
+    """Distinct probable s-t paths.  Each draw perturbs the weights -log(p_e)
+    by independent Exp(1) factors (PCG64, `seed`), builds the shortest-path
+    trees of s and t, and joins them through random via nodes; loop erasure
+    makes every joined walk a simple path, i.e. a minimal path set."""
     s = graph["source"] if s is None else s
     t = graph["sink"] if t is None else t
     n = graph["n_nodes"]
@@ -107,71 +114,119 @@ def sample_paths(graph, p_edge, count, seed, s=None, t=None, max_calls=None):
     for e in range(E):
         eid[(int(eu[e]), int(ev[e]))] = e
         eid[(int(ev[e]), int(eu[e]))] = e
-    rows = np.concatenate([eu, ev])
-    cols = np.concatenate([ev, eu])
-    found = []
-    seen = set()
-    max_calls = max_calls or 20 * count + 100
-    calls = 0
-    while len(found) < count and calls < max_calls:
-        calls += 1
+    rows, cols = _csr_parts(graph)
+    found, seen = [], set()
+    max_draws = max_draws or (20 * count) // vias_per_draw + 100
+    draws = 0
+    while len(found) < count and draws < max_draws:
+        draws += 1
         w = base * rng.exponential(1.0, E) + 1e-9
         mat = csr_matrix((np.concatenate([w, w]), (rows, cols)), shape=(n, n))
-        _, pred = dijkstra(mat, directed=True, indices=s, return_predecessors=True)
-        if pred[t] < 0:
-            continue
-        path = []
-        v = t
-        while v != s:
-            u = int(pred[v])
-            path.append(eid[(u, v)])
-            v = u
-        key = tuple(sorted(path))
-        if key not in seen:
-            seen.add(key)
-            found.append(key)
+        _, pred = dijkstra(mat, directed=True, indices=[s, t], return_predecessors=True)
+        ps, pt = pred[0], pred[1]
+        for v in rng.permutation(n)[:vias_per_draw]:
+            v = int(v)
+            if v != s and ps[v] < 0:
+                continue
+            # s -> v along the tree of s, then v -> t along the tree of t
+            a = [v]
+            while a[-1] != s:
+                a.append(int(ps[a[-1]]))
+            a.reverse()
+            b = v
+            seq = list(a)
+            while b != t:
+                b = int(pt[b])
+                seq.append(b)
+            # loop erasure
+            pos, walk = {}, []
+            for node in seq:
+                if node in pos:
+                    k = pos[node]
+                    for dropped in walk[k + 1:]:
+                        del pos[dropped]
+                    walk = walk[:k + 1]
+                else:
+                    pos[node] = len(walk)
+                    walk.append(node)
+            key = tuple(sorted(eid[(walk[i], walk[i + 1])] for i in range(len(walk) - 1)))
+            if key not in seen:
+                seen.add(key)
+                found.append(key)
+                if len(found) >= count:
+                    break
     return found
 
 
-def sample_cuts(graph, count, seed, s=None, t=None, mean_size=4.0, max_attempts=None):
-    """Distinct minimal s-t cuts from random connected growth.
-
-    A node set T is grown from t (or, alternately, from s) by a geometric
-    number of random neighbour additions; the side holding the other terminal
-    is then taken as the component of the rest that contains it, which makes
-    both sides connected and so the crossing edges a minimal cut."""
+def sample_cuts(graph, count, seed, s=None, t=None, max_draws=None):
+    """Distinct minimal s-t cuts.  Each draw grows a ball around one terminal
+    (alternately the sink and the source) in the order of a shortest-path
+    tree under Exp(1) edge weights (PCG64, `seed`).  For every ball B not
+    holding the other terminal, that terminal's component in V minus B is one
+    side and its complement the other; both are connected, so the crossing
+    edges form a minimal cut.  Components are tracked with a union-find that
+    adds nodes farthest first."""
     s = graph["source"] if s is None else s
     t = graph["sink"] if t is None else t
     n = graph["n_nodes"]
-    adj = _adjacency(graph)
     eu, ev = graph["edge_u"], graph["edge_v"]
+    E = eu.size
+    adj = [[] for _ in range(n)]
+    for a, b in zip(eu.tolist(), ev.tolist()):
+        adj[a].append(b)
+        adj[b].append(a)
     rng = np.random.default_rng(seed)
-    found = []
-    seen = set()
-    max_attempts = max_attempts or 30 * count + 100
-    attempts = 0
-    while len(found) < count and attempts < max_attempts:
-        attempts += 1
-        grow_from, other = (t, s) if attempts % 2 else (s, t)
-        size = int(rng.geometric(1.0 / mean_size))
-        grown = np.zeros(n, dtype=bool)
-        grown[grow_from] = True
-        members = [grow_from]
-        for _ in range(size - 1):
-            cand = [v for u in members for v, _ in adj[u] if not grown[v] and v != other]
-            if not cand:
-                break
-            v = cand[int(rng.integers(len(cand)))]
-            grown[v] = True
-            members.append(v)
-        other_side = _reach(adj, other, grown)
-        side = np.ones(n, dtype=bool)
-        side[list(other_side)] = False
-        cut = np.nonzero(side[eu] != side[ev])[0]
-        key = tuple(int(e) for e in cut)
-        if key and key not in seen:
-            seen.add(key)
-            found.append(key)
+    rows, cols = _csr_parts(graph)
+    found, seen = [], set()
+    max_draws = max_draws or 40 * count // max(1, n // 4) + 200
+    draws = 0
+    while len(found) < count and draws < max_draws:
+        draws += 1
+        center, other = (t, s) if draws % 2 else (s, t)
+        w = rng.exponential(1.0, E) + 1e-9
+        mat = csr_matrix((np.concatenate([w, w]), (rows, cols)), shape=(n, n))
+        dist = dijkstra(mat, directed=True, indices=center)
+        order = np.argsort(dist, kind="stable").tolist()
+        kmax = order.index(other)  # the ball may hold order[:k] for k <= kmax
+        # union-find over the complement, adding nodes farthest-first
+        parent = list(range(n))
+        members = {}
+
+        def find(x):
+            while parent[x] != x:
+                parent[x] = parent[parent[x]]
+                x = parent[x]
+            return x
+
+        active = np.zeros(n, dtype=bool)
+        in_side = np.zeros(n, dtype=bool)
+        last_size = -1
+        for k in range(n - 1, 0, -1):
+            node = order[k]
+            active[node] = True
+            members[node] = [node]
+            for nb in adj[node]:
+                if active[nb]:
+                    ra, rb = find(node), find(nb)
+                    if ra != rb:
+                        if len(members[ra]) < len(members[rb]):
+                            ra, rb = rb, ra
+                        parent[rb] = ra
+                        members[ra].extend(members.pop(rb))
+            if k > kmax:
+                continue
+            side = members[find(other)]
+            if len(side) == last_size:  # the side only grows: same size, same set
+                continue
+            last_size = len(side)
+            in_side[:] = False
+            in_side[side] = True
+            key = tuple(np.nonzero(in_side[eu] != in_side[ev])[0].tolist())
+            if key and key not in seen:
+                seen.add(key)
+                found.append(key)
+                if len(found) >= count:
+                    break
     return found
 
 
