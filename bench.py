@@ -27,6 +27,14 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # MI355X dense int8 matrix-core peak (AMD's published figure, no sparsity).
 MFMA_I8_PEAK_OPS = 5.0e15
+# HBM bytes per launch of the COUNT-mode classification on the graph2 workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
+# (profiles/bench_graph2_hbm_traffic.md).  Set an entry to None when its kernel
+# changes, until the counters are taken again.
+COUNT_TRAFFIC_BYTES = {
+    "popcount": (50.42 + 0.95) * 2 ** 20,
+    "mfma": (334.93 + 0.95) * 2 ** 20,
+}
 
 
 def log(msg):
@@ -47,7 +55,19 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=0.25,
                     help="reference rows of the batched workload, as a fraction of its sizes")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 4 times (calibrates the HBM "
+                         "byte counters of rocprofv3) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB x 4")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
               "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
@@ -177,7 +197,9 @@ def main():
             "peak": (VALU_PEAK_OPS if dom == "popcount" else MFMA_I8_PEAK_OPS) / 1e12,
             "unit": "TOP/s",
             "frac": achieved / (VALU_PEAK_OPS if dom == "popcount" else MFMA_I8_PEAK_OPS),
-            "traffic": None,
+            "traffic": COUNT_TRAFFIC_BYTES.get(dom),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+            "algorithmic_bytes": 4.0 * W * N + (R_L + R_U) * 4.0 * W + N,
             "ops_per_test": W if dom == "popcount" else 2 * KP,
             "kernel_ms": count_ms,
         },

@@ -56,50 +56,84 @@ __device__ __forceinline__ int64_t block_reserve(bool carry, unsigned long long*
     return slot;
 }
 
-// Tests S samples per lane against rows [l0, l1) (lower) and [u0, u1)
-// (upper), interleaved; returns the OR-accumulated violation minima.
+// Rows per side staged in LDS at a time (at most 32 KB for both sides).
+template <int W>
+constexpr int tile_rows() {
+    return 4096 / W > 64 ? 64 : (4096 / W < 8 ? 8 : 4096 / W);
+}
+
+// Block-level: tests S samples per lane against rows [l0, l1) (lower) and
+// [u0, u1) (upper), interleaved.  The rows pass through LDS in tiles (one
+// coalesced cooperative load per tile; the reads are wave-uniform, so every
+// LDS access is a broadcast).  A wave stops testing once all its live lanes
+// have matched (vote every 8 rows); the block leaves when every wave has.
+// Every thread of the block must call it.
 template <int W, int S>
 __device__ __forceinline__ void test_rows(const uint32_t (&x)[S][W], const uint32_t (&nx)[S][W],
                                           const bool (&live)[S], const uint32_t* __restrict__ low_n,
                                           int l0, int l1, const uint32_t* __restrict__ up_b,
                                           int u0, int u1, uint32_t (&mnL)[S],
-                                          uint32_t (&mnU)[S]) {
+                                          uint32_t (&mnU)[S], uint32_t* lds) {
+    constexpr int T = tile_rows<W>();
     const int nL = l1 - l0, nU = u1 - u0;
     const int n_max = nL > nU ? nL : nU;
-    for (int r0 = 0; r0 < n_max; r0 += 8) {
+    bool any_live = false;
 #pragma unroll
-        for (int r = r0; r < r0 + 8; ++r) {
-            if (r < nL) {
-                const uint32_t* row = low_n + static_cast<int64_t>(l0 + r) * W;
-                uint32_t rw[W];
+    for (int s = 0; s < S; ++s) any_live = any_live || live[s];
+    bool wave_done = !__any(any_live);
+    const uint32_t* lo_src = low_n + static_cast<int64_t>(l0) * W;
+    const uint32_t* up_src = up_b + static_cast<int64_t>(u0) * W;
+    for (int t0 = 0; t0 < n_max; t0 += T) {
+        __syncthreads();
+        const int lo_words = (nL - t0 < T ? (nL - t0 > 0 ? nL - t0 : 0) : T) * W;
+        const int up_words = (nU - t0 < T ? (nU - t0 > 0 ? nU - t0 : 0) : T) * W;
+        for (int k = threadIdx.x; k < T * W; k += kBlock) {
+            lds[k] = k < lo_words ? lo_src[static_cast<int64_t>(t0) * W + k] : 0u;
+            lds[T * W + k] = k < up_words ? up_src[static_cast<int64_t>(t0) * W + k] : 0u;
+        }
+        __syncthreads();
+        if (!wave_done) {
+            const int cnt = n_max - t0 < T ? n_max - t0 : T;
+            for (int r0 = 0; r0 < cnt; r0 += 8) {
 #pragma unroll
-                for (int w = 0; w < W; ++w) rw[w] = row[w];
+                for (int r = r0; r < r0 + 8; ++r) {
+                    if (t0 + r < nL) {
+                        const uint32_t* row = lds + r * W;
+                        uint32_t rw[W];
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    uint32_t t = 0;
+                        for (int w = 0; w < W; ++w) rw[w] = row[w];
 #pragma unroll
-                    for (int w = 0; w < W; ++w) t = (x[s][w] & rw[w]) | t;
-                    mnL[s] = min(mnL[s], t);
+                        for (int s = 0; s < S; ++s) {
+                            uint32_t t = 0;
+#pragma unroll
+                            for (int w = 0; w < W; ++w) t = (x[s][w] & rw[w]) | t;
+                            mnL[s] = min(mnL[s], t);
+                        }
+                    }
+                    if (t0 + r < nU) {
+                        const uint32_t* row = lds + T * W + r * W;
+                        uint32_t rw[W];
+#pragma unroll
+                        for (int w = 0; w < W; ++w) rw[w] = row[w];
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            uint32_t t = 0;
+#pragma unroll
+                            for (int w = 0; w < W; ++w) t = (nx[s][w] & rw[w]) | t;
+                            mnU[s] = min(mnU[s], t);
+                        }
+                    }
                 }
-            }
-            if (r < nU) {
-                const uint32_t* row = up_b + static_cast<int64_t>(u0 + r) * W;
-                uint32_t rw[W];
+                bool done = true;
 #pragma unroll
-                for (int w = 0; w < W; ++w) rw[w] = row[w];
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    uint32_t t = 0;
-#pragma unroll
-                    for (int w = 0; w < W; ++w) t = (nx[s][w] & rw[w]) | t;
-                    mnU[s] = min(mnU[s], t);
+                for (int s = 0; s < S; ++s) done = done && (!live[s] || mnL[s] == 0u || mnU[s] == 0u);
+                if (__all(done)) {
+                    wave_done = true;
+                    break;
                 }
             }
         }
-        bool done = true;
-#pragma unroll
-        for (int s = 0; s < S; ++s) done = done && (!live[s] || mnL[s] == 0u || mnU[s] == 0u);
-        if (__all(done)) break;
+        if (__syncthreads_and(wave_done ? 1 : 0)) break;
     }
 }
 
@@ -113,9 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
     unsigned long long* __restrict__ dst_count, int last) {
     __shared__ int s_counts[kWaves];
     __shared__ unsigned long long s_base;
+    __shared__ uint32_t s_rows[2 * tile_rows<W>() * W];
     const int64_t total = src_idx ? static_cast<int64_t>(*src_count) : seg.total;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // Block-uniform loop (block_reserve synchronises the block).
+    // Block-uniform loop (test_rows and block_reserve synchronise the block).
     for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBlock * S; b0 < total;
          b0 += static_cast<int64_t>(gridDim.x) * kBlock * S) {
         const int64_t j0 = b0 + static_cast<int64_t>(wave) * 64 * S;
@@ -143,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
         uint32_t mnL[S], mnU[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
-        if (__any(valid[0])) test_rows<W, S>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU);
+        test_rows<W, S>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const bool hit = mnL[s] == 0u || mnU[s] == 0u;
@@ -182,14 +217,13 @@ __global__ __launch_bounds__(kBlock) void k_casc_test(
     const int cl1 = l0 + static_cast<int>((static_cast<int64_t>(nL) * (c + 1)) / chunks);
     const int cu0 = u0 + static_cast<int>((static_cast<int64_t>(nU) * c) / chunks);
     const int cu1 = u0 + static_cast<int>((static_cast<int64_t>(nU) * (c + 1)) / chunks);
-    const int lane = threadIdx.x & 63;
-    const int64_t wave_id = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t wave_stride = static_cast<int64_t>(gridDim.x) * kWaves;
-    for (int64_t j0 = wave_id * 64; j0 < total; j0 += wave_stride * 64) {
-        const int64_t d = j0 + lane;
+    __shared__ uint32_t s_rows[2 * tile_rows<W>() * W];
+    // Block-uniform loop (test_rows synchronises the block).
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBlock; b0 < total;
+         b0 += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t d = b0 + threadIdx.x;
         bool live[1];
         live[0] = d < total && match[d] == 0u;
-        if (!__any(live[0])) continue;
         uint32_t x[1][W], nx[1][W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -197,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_test(
             nx[0][w] = ~x[0][w];
         }
         uint32_t mnL[1] = {0xFFFFFFFFu}, mnU[1] = {0xFFFFFFFFu};
-        test_rows<W, 1>(x, nx, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU);
+        test_rows<W, 1>(x, nx, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU, s_rows);
         const uint32_t bits = (mnL[0] == 0u ? 1u : 0u) | (mnU[0] == 0u ? 2u : 0u);
         if (live[0] && bits) atomicOr(&match[d], bits);
     }

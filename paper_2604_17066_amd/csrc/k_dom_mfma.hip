@@ -21,7 +21,8 @@
 // LABEL mode keeps, per sample, the unsigned minimum of its accumulators (0 =
 // some row matched), and the block leaves a pass early when every sample is
 // decided (vote every 4 tiles; lower-flagged samples are decided for the upper
-// pass).  COUNT mode counts zero accumulators exactly.
+// pass).  COUNT mode counts the non-zero accumulators (sum of min(acc, 1)) and
+// returns rows - non-zeros, the exact number of matching rows.
 #include "rsr_internal.h"
 
 namespace rsr {
@@ -44,20 +45,24 @@ __device__ __forceinline__ uint32_t umin4(v4i a) {
     return min(min(x, y), min(z, w));
 }
 
-__device__ __forceinline__ uint32_t zeros4(v4i a) {
-    return (a.x == 0 ? 1u : 0u) + (a.y == 0 ? 1u : 0u) + (a.z == 0 ? 1u : 0u) +
-           (a.w == 0 ? 1u : 0u);
+// Number of non-zero accumulators among four (min(v, 1) is 0 or 1 as unsigned).
+__device__ __forceinline__ uint32_t nonzeros4(v4i a) {
+    return min(static_cast<uint32_t>(a.x), 1u) + min(static_cast<uint32_t>(a.y), 1u) +
+           min(static_cast<uint32_t>(a.z), 1u) + min(static_cast<uint32_t>(a.w), 1u);
 }
 
 // One pass over the tiles of one side.  acc_out[t] = running min (LABEL) or
-// count (COUNT) for this lane's column of sample tile t.
+// number of non-zero accumulators (COUNT) for this lane's column of sample
+// tile t.  An LDS tile holds the KS*64 operand fragments followed by the 16
+// accumulator starts, so the loop has no global load on its critical path.
 template <int KS, int MT, bool COUNT>
 __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
                                           const v4i* __restrict__ cinit, int tiles,
                                           v4i* __restrict__ lds, uint32_t (&acc_out)[MT],
                                           const bool (&pre_done)[MT], const bool (&valid)[MT],
                                           int* vote) {
-    constexpr int kTileV4 = KS * 64;  // v4i per reference tile
+    constexpr int kFragV4 = KS * 64;      // operand v4i per reference tile
+    constexpr int kTileV4 = kFragV4 + 4;  // plus 16 accumulator starts
     constexpr int kPerThread = (kTileV4 + kBlock - 1) / kBlock;
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4;
@@ -68,7 +73,10 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
 #pragma unroll
         for (int q = 0; q < kPerThread; ++q) {
             const int idx = q * kBlock + threadIdx.x;
-            if (idx < kTileV4) stage[q] = frag[static_cast<int64_t>(T) * kTileV4 + idx];
+            if (idx < kFragV4)
+                stage[q] = frag[static_cast<int64_t>(T) * kFragV4 + idx];
+            else if (idx < kTileV4)
+                stage[q] = cinit[static_cast<int64_t>(T) * 4 + (idx - kFragV4)];
         }
     };
     auto store = [&](int buf) {
@@ -85,7 +93,7 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
     for (int T = 0; T < tiles; ++T) {
         const int cur = T & 1;
         if (T + 1 < tiles) fetch(T + 1);
-        const v4i c0 = cinit[static_cast<int64_t>(T) * 4 + grp];
+        const v4i c0 = lds[cur * kTileV4 + kFragV4 + grp];
         v4i a[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s) a[s] = lds[cur * kTileV4 + s * 64 + lane];
@@ -100,7 +108,7 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
             if (COUNT)
-                acc_out[t] += zeros4(acc[t]);
+                acc_out[t] += nonzeros4(acc[t]);
             else
                 acc_out[t] = min(acc_out[t], umin4(acc[t]));
         }
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     const v4i* __restrict__ low_c, int TL, const v4i* __restrict__ up_frag,
     const v4i* __restrict__ up_c, int TU, uint8_t* __restrict__ flags,
     uint32_t* __restrict__ match) {
-    __shared__ v4i lds[2 * KS * 64];
+    __shared__ v4i lds[2 * (KS * 64 + 4)];
     __shared__ int vote[kWaves];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -173,7 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     }
     mfma_pass<KS, MT, COUNT>(bf, low_frag, low_c, TL, lds, accL, none, valid, vote);
 
-    // Per-sample lower result across the four lane groups.
+    // Per-sample lower result across the four lane groups (COUNT: every one of
+    // the 16 TL rows is either a zero or a non-zero accumulator).
     bool lowered[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -181,6 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
         if (COUNT) {
             m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16));
             m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32));
+            m = 16u * static_cast<uint32_t>(TL) - m;
         } else {
             m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16)));
             m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32)));
@@ -210,6 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
         if (COUNT) {
             m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16));
             m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32));
+            m = 16u * static_cast<uint32_t>(TU) - m;
         } else {
             m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16)));
             m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32)));

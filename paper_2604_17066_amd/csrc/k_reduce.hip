@@ -181,29 +181,48 @@ __global__ __launch_bounds__(kBlock) void k_grad_finalize(const uint32_t* __rest
         ypart += static_cast<int64_t>(blockIdx.y) * job_stride;
         if (!G) return;
     }
-    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    // One wavefront per (i, s); its lanes add the per-block partials.
+    const int lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (idx >= n * K) return;
     const int i = idx / K, s = idx % K;
     // a(j) = #{h : Y_h = 1 and x_{h,i} >= j}; a(0) = #{Y = 1}; a(K) = 0.
     auto level_count = [&](int j) -> unsigned long long {
         unsigned long long t = 0;
         if (j == 0) {
-            for (int b = 0; b < bx; ++b) t += ypart[b];
+            for (int b = lane; b < bx; b += 64) t += ypart[b];
         } else if (j < K) {
             const int w = (j - 1) * PW + (i >> 5);
             const uint32_t* col = partial + static_cast<int64_t>(w) * bx * 32 + (i & 31);
-            for (int b = 0; b < bx; ++b) t += col[static_cast<int64_t>(b) * 32];
+            for (int b = lane; b < bx; b += 64) t += col[static_cast<int64_t>(b) * 32];
         }
-        return t;
+        return wave_sum(t);
     };
     const unsigned long long cnt = level_count(s) - level_count(s + 1);
-    const float pv = p[idx];
-    const float g = pv > 0.0f ? static_cast<float>(cnt) / (static_cast<float>(N) * pv) : 0.0f;
-    G[idx] = g;
-    if (counts) counts[idx] = cnt;
+    if (lane == 0) {
+        const float pv = p[idx];
+        const float g = pv > 0.0f ? static_cast<float>(cnt) / (static_cast<float>(N) * pv) : 0.0f;
+        G[idx] = g;
+        if (counts) counts[idx] = cnt;
+    }
+}
+
+// Copies every job's gradient into one buffer (out + job.g_off), so a plan
+// returns all gradients with a single device-to-host copy.
+__global__ __launch_bounds__(kBlock) void k_gather_G(const JobDev* __restrict__ jobs, int nK,
+                                                     float* __restrict__ out) {
+    const JobDev& jd = jobs[blockIdx.y];
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx < nK && jd.G) out[jd.g_off + idx] = jd.G[idx];
 }
 
 }  // namespace
+
+hipError_t launch_gather_G(hipStream_t st, const JobDev* jobs, int n_jobs, int nK, float* out) {
+    hipLaunchKernelGGL(k_gather_G, dim3((nK + kBlock - 1) / kBlock, n_jobs), dim3(kBlock), 0, st,
+                       jobs, nK, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value) {
     const dim3 grid(static_cast<unsigned>((count + kBlock - 1) / kBlock));
@@ -252,7 +271,9 @@ hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uin
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int total = n * K;
-    hipLaunchKernelGGL(k_grad_finalize, dim3((total + kBlock - 1) / kBlock, nj), dim3(kBlock), 0, st,
+    const int waves_per_block = kBlock / 64;
+    hipLaunchKernelGGL(k_grad_finalize, dim3((total + waves_per_block - 1) / waves_per_block, nj),
+                       dim3(kBlock), 0, st,
                        d_partial, ypart, static_cast<int>(bx), d_p, n, K, PW, N, d_G,
                        reinterpret_cast<unsigned long long*>(d_counts), jobs, job_stride);
     return hipGetLastError();

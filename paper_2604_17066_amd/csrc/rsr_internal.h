@@ -90,6 +90,7 @@ struct JobDev {
     uint64_t seed;
     uint32_t stream_id;
     int32_t n, K;
+    int64_t g_off;           // offset of this job's gradient in a plan's gather buffer
 };
 
 // Where a kernel finds its samples: one job (jobs == nullptr: samples / N /
@@ -195,6 +196,7 @@ int64_t grad_blocks(int64_t N);
 hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uint32_t* d_samples,
                        const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
                        uint64_t* d_counts, const JobDev* jobs = nullptr, int n_jobs = 1);
+hipError_t launch_gather_G(hipStream_t st, const JobDev* jobs, int n_jobs, int nK, float* out);
 hipError_t launch_sample_jobs(hipStream_t st, int n, int K, const JobDev* jobs,
                               const int64_t* offsets, int n_jobs, int64_t total, int grid_cap);
 hipError_t launch_copy_u64(hipStream_t st, const uint64_t* src, uint64_t* dst, int count);

@@ -54,6 +54,10 @@ struct rsr_plan {
     std::vector<int64_t> offset_base;
     uint64_t* d_counts = nullptr;     // [jobs][8]
     uint64_t* h_counts = nullptr;     // pinned [jobs][8]
+    float* d_G_all = nullptr;         // every job's gradient, gathered (job.g_off)
+    float* h_G_all = nullptr;         // pinned copy
+    int64_t G_total = 0;
+    std::vector<int64_t> host_g_off;  // device position -> offset in the gather buffer
     uint64_t* d_count_part = nullptr;
     uint32_t* d_grad_part = nullptr;
     uint32_t* d_casc_words = nullptr;
@@ -150,6 +154,8 @@ hipError_t enqueue_rest(const rsr_plan* p, int si, hipStream_t st) {
     if (e == hipSuccess && s.any_grad)
         e = rsr::launch_grad(st, s.n, s.K, nullptr, nullptr, nullptr, s.max_N, p->d_grad_part,
                              nullptr, nullptr, p->d_jobs + s.first_pos, nj);
+    if (e == hipSuccess && s.any_grad)
+        e = rsr::launch_gather_G(st, p->d_jobs + s.first_pos, nj, s.n * s.K, p->d_G_all);
     if (e == hipSuccess)
         e = rsr::launch_counts(st, nullptr, nullptr, s.max_N,
                                p->d_counts + static_cast<int64_t>(s.first_pos) * 8,
@@ -175,8 +181,10 @@ rsr_status tune_segment(rsr_plan* p, int si) {
             for (int g : growths)
                 for (int sp : splits) cands.push_back({kCascade, rsr::CascadeShape{f, g, sp}});
     }
-    cands.push_back({kBitsPerJob, rsr::CascadeShape{}});
-    if (s.refs->KS > 0) cands.push_back({kMfmaPerJob, rsr::CascadeShape{}});
+    if (!s.refs->consistent) {
+        cands.push_back({kBitsPerJob, rsr::CascadeShape{}});
+        if (s.refs->KS > 0) cands.push_back({kMfmaPerJob, rsr::CascadeShape{}});
+    }
     PLAN_HIP(ctx, enqueue_sample(p, si, p->cap));
     hipEvent_t a, b;
     PLAN_HIP(ctx, hipEventCreate(&a));
@@ -212,6 +220,8 @@ void free_plan(rsr_plan* p) {
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->h_counts) (void)hipHostFree(p->h_counts);
+    if (p->h_G_all) (void)hipHostFree(p->h_G_all);
+    if (p->d_G_all) (void)hipFree(p->d_G_all);
     delete p;
 }
 
@@ -295,6 +305,9 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
             d.stream_id = jb.stream_id;
             d.n = s.n;
             d.K = s.K;
+            d.g_off = p->G_total;
+            p->host_g_off.push_back(p->G_total);
+            p->G_total += static_cast<int64_t>(s.n) * s.K;
             host_jobs.push_back(d);
             host_offsets.push_back(off);
             off += jb.N;
@@ -325,8 +338,12 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
     dmalloc(reinterpret_cast<void**>(&p->d_casc_counters), sizeof(uint64_t) * 16);
     dmalloc(reinterpret_cast<void**>(&p->d_list), sizeof(int32_t) * max_total);
     dmalloc(reinterpret_cast<void**>(&p->d_list_counter), sizeof(uint64_t) * 2);
+    dmalloc(reinterpret_cast<void**>(&p->d_G_all), sizeof(float) * p->G_total);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&p->h_counts), sizeof(uint64_t) * 8 * n_jobs,
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&p->h_G_all), sizeof(float) * (p->G_total + 1),
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_jobs, host_jobs.data(), sizeof(rsr::JobDev) * host_jobs.size(),
@@ -365,6 +382,9 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_counts, p->d_counts, sizeof(uint64_t) * 8 * n_jobs,
+                           hipMemcpyDeviceToHost, p->cap);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_G_all, p->d_G_all, sizeof(float) * p->G_total,
                            hipMemcpyDeviceToHost, p->cap);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
@@ -411,8 +431,7 @@ rsr_status rsr_plan_results(rsr_plan* p, rsr_estimate_t* est, float* G_host) {
         o.cov = P > 0.0 ? std::sqrt((1.0 - P) / (Nd * P)) : HUGE_VAL;
         const size_t gsz = static_cast<size_t>(jb.model->n) * jb.model->K;
         if (G_host && jb.d_G)
-            PLAN_HIP(ctx, hipMemcpy(G_host + g_off, jb.d_G, sizeof(float) * gsz,
-                                    hipMemcpyDeviceToHost));
+            std::memcpy(G_host + g_off, p->h_G_all + p->host_g_off[p->pos[j]], sizeof(float) * gsz);
         g_off += gsz;
     }
     return RSR_OK;
