@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# RSR_ORACLE_LIB lets the mutation test load a deliberately broken build.
+_LIB_PATH = os.environ.get("RSR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)

@@ -1,0 +1,74 @@
+"""Mutation check of the oracle's pins (CPU only).
+
+Each mutant is a copy of oracle/oracle.c with one plausible mistake planted
+(a swapped constant, an off-by-one, a flipped comparison, a dropped term, a
+wrong index).  It is compiled to a temporary library and the pin suite
+(test_oracle_pins.py) runs against it in a subprocess; every mutant must make
+at least one pin fail.  This shows that the pins constrain every part of the
+oracle, not only that the oracle passes them."""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = {
+    "philox multipliers swapped": ("const uint32_t mulA = 0xD2511F53u, mulB = 0xCD9E8D57u;",
+                                   "const uint32_t mulA = 0xCD9E8D57u, mulB = 0xD2511F53u;"),
+    "philox second key not bumped": ("k1 += weyl1;", "k1 += 0u;"),
+    "philox output words permuted": ("out[0] = c0; out[1] = c1;", "out[0] = c1; out[1] = c0;"),
+    "counter: component group i/8": ("uint32_t ctr[4] = {(uint32_t)(i >> 2),",
+                                      "uint32_t ctr[4] = {(uint32_t)(i >> 3),"),
+    "draw: wrong word of the block": ("return out[i & 3];", "return out[(i + 1) & 3];"),
+    "threshold: cumulative off by one state": ("acc = acc + p[(size_t)i * K + (s - 1)];",
+                                               "acc = acc + p[(size_t)i * K + s];"),
+    "state: strict threshold comparison": ("if (u >= C[(size_t)i * (K - 1) + (s - 1)]) state += 1;",
+                                           "if (u > C[(size_t)i * (K - 1) + (s - 1)]) state += 1;"),
+    "lower test: >= instead of >": ("if (x[i] > r[i]) return 0;", "if (x[i] >= r[i]) return 0;"),
+    "upper test: <= instead of <": ("if (x[i] < r[i]) return 0;", "if (x[i] <= r[i]) return 0;"),
+    "no lower precedence": ("if (mode == 1 || cl == 0) {", "if (1) {"),
+    "Phi ignores the level": ("if ((int)x[e] < level) continue;", "if ((int)x[e] < 1) continue;"),
+    "Phi: lower-flagged samples get Y = 1": ("if (which == 0 && (flags[h] & 1)) {\n            Y[h] = 0;",
+                                             "if (which == 0 && (flags[h] & 1)) {\n            Y[h] = 1;"),
+    "estimate drops evaluated unknowns": ("double P = (double)(counts[1] + counts[4]) / Nd;",
+                                          "double P = (double)(counts[1]) / Nd;"),
+    "coefficient of variation inverted": ("sqrt((1.0 - P) / (Nd * P))", "sqrt(P / (Nd * (1.0 - P)))"),
+    "gradient counts the wrong state": ("counts[(size_t)i * K + xh[i]] += 1;",
+                                        "counts[(size_t)i * K + (K - 1 - xh[i])] += 1;"),
+    "gradient divides by the wrong probability": (
+        "(double)counts[(size_t)i * K + s] / ((double)N * pv)",
+        "(double)counts[(size_t)i * K + s] / ((double)N * p[(size_t)i * K])"),
+    "brute force: state probability uses state 0": ("for (int i = 0; i < n; ++i) prob *= p[(size_t)i * K + x[i]];\n        P += prob;",
+                                                     "for (int i = 0; i < n; ++i) prob *= p[(size_t)i * K];\n        P += prob;"),
+    "paper encoding: down-set strict": ("(m <= (int)r[i] ? 1 : 0)", "(m < (int)r[i] ? 1 : 0)"),
+    "counts: both-flag samples counted upper": ("if (lo) nL += 1;\n        else if (up) nU += 1;",
+                                               "if (lo && !up) nL += 1;\n        else if (up) nU += 1;"),
+}
+
+
+def _run(name, old, new, tmp):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site not found: {name}"
+    path_c = os.path.join(tmp, f"m{abs(hash(name))}.c")
+    path_so = path_c[:-2] + ".so"
+    open(path_c, "w").write(src.replace(old, new, 1))
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", path_so, path_c, "-lm"], check=True, capture_output=True)
+    env = dict(os.environ, RSR_ORACLE_LIB=path_so, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+def test_every_mutant_is_killed():
+    with tempfile.TemporaryDirectory() as tmp:
+        with cf.ThreadPoolExecutor(max_workers=4) as ex:
+            results = list(ex.map(lambda kv: _run(kv[0], kv[1][0], kv[1][1], tmp), MUTANTS.items()))
+    survivors = [name for name, rc in results if rc == 0]
+    assert not survivors, f"mutants not caught by any pin: {survivors}"

@@ -50,6 +50,19 @@ def test_sample_counter_layout_and_thresholds():
 
 # ------------------------------------------------------------- thresholds ----
 
+def test_state_flips_exactly_at_the_threshold():
+    """x = 1 iff u >= C: the first word of sample 0 under seed 0, stream 0 is
+    the first Random123 known-answer word 0x6627E8D5; a failure probability
+    of exactly that word / 2^32 puts the threshold on it (state 1), one more
+    unit puts it above (state 0)."""
+    word = 0x6627E8D5
+    for c, want in ((word, 1), (word + 1, 0), (word - 1, 1)):
+        q = c / 4294967296.0          # exact in fp64
+        p = np.array([[q, 1.0 - q]])
+        assert int(oracle.thresholds(p)[0, 0]) == c
+        assert int(oracle.sample(p, 0, 0, 0, 1)[0, 0]) == want
+
+
 def test_thresholds_exact_edges():
     two32 = 1 << 32
     p_surv = np.array([0.0, 1.0, 0.5, 2.0 ** -32, 1.0 - 2.0 ** -53])
@@ -205,6 +218,10 @@ def test_estimator_closed_forms():
     assert est[3] == 0.5
     assert est[4] == math.sqrt(0.5 * 0.5 / 100)
     assert est[5] == math.sqrt(0.5 / (100 * 0.5))
+    est = oracle.estimate([70, 20, 10, 0, 5, 100])
+    assert est[3] == 0.25
+    assert abs(est[4] - math.sqrt(0.25 * 0.75 / 100)) < 1e-15
+    assert abs(est[5] - math.sqrt(0.75 / (100 * 0.25))) < 1e-15
     zero = oracle.estimate([100, 0, 0, 0, 0, 100])
     assert zero[3] == 0.0 and math.isinf(zero[5])
 
@@ -242,6 +259,26 @@ def test_closed_forms_series_parallel_bridge():
     P, _ = oracle.exact(oracle.state_probs_binary(pb), oracle.phi_table_st(_bridge()),
                         want_grad=False)
     assert abs(P - _bridge_closed_form(pb)) < 1e-14
+
+
+def test_closed_forms_multistate_levels():
+    """Bottleneck levels of 3-state series and parallel systems: S >= k needs
+    every (series) or some (parallel) edge in a state >= k."""
+    rng = np.random.default_rng(9)
+    n = 6
+    p = rng.dirichlet([1.0, 1.5, 2.0], size=n)
+    series = _graph(n + 1, [(i, i + 1) for i in range(n)], 0, n)
+    parallel = _graph(2, [(0, 1)] * n, 0, 1)
+    for level in (1, 2):
+        ge = p[:, level:].sum(axis=1)
+        for g, want in [(series, np.prod(ge)), (parallel, 1 - np.prod(1 - ge))]:
+            P, _ = oracle.exact(p, oracle.phi_table_st(g, K=3, level=level), want_grad=False)
+            assert abs(P - want) < 1e-13
+    x = np.array([[2, 2, 1, 2, 2, 2]], dtype=np.uint8)
+    assert oracle.phi_st(series, x[0], level=1) == 1
+    assert oracle.phi_st(series, x[0], level=2) == 0
+    Y, _ = oracle.eval_unknown(series, x, None, which=1, level=2)
+    assert Y.tolist() == [0]
 
 
 def test_exact_partials_against_closed_form_derivatives():
