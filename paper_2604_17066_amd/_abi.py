@@ -7,7 +7,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librsr.so")
+# RSR_LIB names another build of the same library (for example one built with
+# different kernel options); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("RSR_LIB") or os.path.join(_HERE, "librsr.so")
 
 RSR_OK, RSR_EINVAL, RSR_ENOMEM, RSR_EHIP, RSR_EUNSUPPORTED = 0, 1, 2, 3, 4
 RSR_LABEL, RSR_COUNT = 0, 1

@@ -2,11 +2,13 @@
 // paper (section 3.3.2, eq. violation_matrix) as an int8 contraction on the
 // gfx950 MFMA units, with int32 accumulation.
 //
-// Operands are the thermometer bits of rsr.h as 0/1 bytes, k = packed bit
-// index.  For a lower row r the contraction is V = sum_k t(x)_k * NOT t(r)_k,
-// zero iff x <= r.  For an upper row it is sum_k t(x)_k * t(r)_k, which equals
-// |t(r)| iff x >= r; the accumulator starts at -|t(r)| so that both sides are a
-// zero test.  Pad rows (R rounded up to 16) start at +1 and never match.
+// Operands are the thermometer bits of rsr.h as bytes, k = packed bit index,
+// encoded so that a row matches exactly when its accumulator is negative.  For
+// a lower row r the A bytes are NOT t(r) in {0, 1} and the accumulator starts
+// at -1: the result is |t(x) & ~t(r)| - 1, negative iff x <= r.  For an upper
+// row the A bytes are -t(r) in {0, -1} and the start is |t(r)| - 1: the result
+// is |t(r)| - |t(r) & t(x)| - 1 = |t(r) & ~t(x)| - 1, negative iff x >= r.
+// Pad rows (R rounded up to 16) and pad tiles are all zero and never match.
 //
 // One v_mfma_i32_16x16x64_i8 multiplies a 16 x 64 tile of reference rows (A)
 // by a 64 x 16 tile of samples (B).  Lane l supplies row / column l % 16 and
@@ -14,15 +16,18 @@
 // 4 (l / 16) .. +3 of column l % 16.  A wave keeps the B fragments of MT
 // sample tiles (16 MT samples) in VGPRs for the whole kernel (expanded once
 // from the packed bits); the eight waves of a block share reference tiles,
-// which are staged through LDS with double buffering.  Reference rows are
-// stored on the device in fragment order ([tile][k-step][lane][16 bytes]), so a
-// tile is one contiguous block and every LDS read is one 16-byte access.
+// which are staged through LDS with double buffering, several tiles per
+// barrier.  Reference rows are stored on the device in fragment order
+// ([tile][k-step][lane][16 bytes]), so a tile is one contiguous block and every
+// LDS read is one 16-byte access.
 //
-// LABEL mode keeps, per sample, the unsigned minimum of its accumulators (0 =
-// some row matched), and the block leaves a pass early when every sample is
-// decided (vote every 4 tiles; lower-flagged samples are decided for the upper
-// pass).  COUNT mode counts the non-zero accumulators (sum of min(acc, 1)) and
-// returns rows - non-zeros, the exact number of matching rows.
+// The accumulators of a tile are folded into the per-sample result while the
+// matrix products of the next tile run, so the VALU work hides under the
+// MFMA pipe.  COUNT mode counts negative accumulators (a byte-sign permute and
+// a popcount per pair, so 8 per match); LABEL mode keeps the signed minimum
+// (negative = some row matched) and the block leaves a pass early when every
+// sample is decided (vote once per staged group; lower-flagged samples are
+// decided for the upper pass).
 #include "rsr_internal.h"
 
 namespace rsr {
@@ -32,96 +37,150 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 512;
 constexpr int kWaves = kBlock / 64;
-constexpr int kVoteTiles = 4;
 
 __device__ __forceinline__ int expand4(uint32_t v) {
     // Bits b0..b3 of v (v < 16) -> bytes b0, b1, b2, b3.
     return static_cast<int>((v * 0x00204081u) & 0x01010101u);
 }
 
-__device__ __forceinline__ uint32_t umin4(v4i a) {
-    const uint32_t x = static_cast<uint32_t>(a.x), y = static_cast<uint32_t>(a.y);
-    const uint32_t z = static_cast<uint32_t>(a.z), w = static_cast<uint32_t>(a.w);
-    return min(min(x, y), min(z, w));
+// acc + 8 * (number of negative lanes of a).  v_perm_b32 selector bytes 9 and
+// 11 replicate bit 31 of the low and high source into a whole byte; 12 gives
+// a zero byte.
+__device__ __forceinline__ uint32_t add_negatives8(v4i a, uint32_t acc) {
+    const uint32_t p0 = __builtin_amdgcn_perm(static_cast<uint32_t>(a.x),
+                                              static_cast<uint32_t>(a.y), 0x0C0C0B09u);
+    const uint32_t p1 = __builtin_amdgcn_perm(static_cast<uint32_t>(a.z),
+                                              static_cast<uint32_t>(a.w), 0x0C0C0B09u);
+    return static_cast<uint32_t>(__builtin_popcount(p1)) +
+           (static_cast<uint32_t>(__builtin_popcount(p0)) + acc);
 }
 
-// Number of non-zero accumulators among four (min(v, 1) is 0 or 1 as unsigned).
-__device__ __forceinline__ uint32_t nonzeros4(v4i a) {
-    return min(static_cast<uint32_t>(a.x), 1u) + min(static_cast<uint32_t>(a.y), 1u) +
-           min(static_cast<uint32_t>(a.z), 1u) + min(static_cast<uint32_t>(a.w), 1u);
+__device__ __forceinline__ int min4(v4i a) { return min(min(a.x, a.y), min(a.z, a.w)); }
+
+template <int MT, bool COUNT>
+__device__ __forceinline__ void fold(const v4i (&r)[MT], int (&acc_out)[MT]) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        if (COUNT)
+            acc_out[t] = static_cast<int>(add_negatives8(r[t], static_cast<uint32_t>(acc_out[t])));
+        else
+            acc_out[t] = min(acc_out[t], min4(r[t]));
+    }
 }
 
-// One pass over the tiles of one side.  acc_out[t] = running min (LABEL) or
-// number of non-zero accumulators (COUNT) for this lane's column of sample
-// tile t.  An LDS tile holds the KS*64 operand fragments followed by the 16
-// accumulator starts, so the loop has no global load on its critical path.
+// Reference tiles staged per barrier: keeps the double-buffered LDS stage at
+// 2 * TPS * KS KB (at most 40 KB) and gives the global loads of the next group
+// TPS tiles of matrix work to land.  (Four tiles per stage makes the compiler
+// hold more than one tile's operands and spill.)
+template <int KS>
+constexpr int tiles_per_stage() {
+    return KS <= 10 ? 2 : 1;
+}
+
+// Sample tiles per wave: B fragments take MT * KS * 4 VGPRs, and with the two
+// accumulator sets of the pipelined fold everything must fit 256 VGPRs (two
+// waves per SIMD) without spilling.
+template <int KS>
+constexpr int sample_tiles() {
+    return KS <= 2 ? 8 : KS == 3 ? 7 : KS == 4 ? 6 : KS == 5 ? 5 : (KS >= 30 ? 1 : 30 / KS);
+}
+
+// One pass over the tiles of one side.  acc_out[t] = 8 * matches (COUNT) or
+// the running signed minimum (LABEL) for this lane's column of sample tile t.
+// An LDS tile holds the KS*64 operand fragments followed by the 16
+// accumulator starts, so the loop has no global load on its critical path;
+// tiles past the end are staged as zeros (never a match), so every group
+// runs all of its tiles without a branch.
 template <int KS, int MT, bool COUNT>
 __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
                                           const v4i* __restrict__ cinit, int tiles,
-                                          v4i* __restrict__ lds, uint32_t (&acc_out)[MT],
+                                          v4i* __restrict__ lds, int (&acc_out)[MT],
                                           const bool (&pre_done)[MT], const bool (&valid)[MT],
                                           int* vote) {
     constexpr int kFragV4 = KS * 64;      // operand v4i per reference tile
     constexpr int kTileV4 = kFragV4 + 4;  // plus 16 accumulator starts
-    constexpr int kPerThread = (kTileV4 + kBlock - 1) / kBlock;
+    constexpr int TPS = tiles_per_stage<KS>();
+    constexpr int kStageV4 = TPS * kTileV4;
+    constexpr int kPerThread = (kStageV4 + kBlock - 1) / kBlock;
+    constexpr int kFoldValu = COUNT ? 4 * MT : 2 * MT;
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4;
     if (tiles <= 0) return;
+    const int groups = (tiles + TPS - 1) / TPS;
 
     v4i stage[kPerThread];
-    auto fetch = [&](int T) {
+    auto fetch = [&](int G) {
 #pragma unroll
         for (int q = 0; q < kPerThread; ++q) {
             const int idx = q * kBlock + threadIdx.x;
-            if (idx < kFragV4)
-                stage[q] = frag[static_cast<int64_t>(T) * kFragV4 + idx];
-            else if (idx < kTileV4)
-                stage[q] = cinit[static_cast<int64_t>(T) * 4 + (idx - kFragV4)];
+            if (idx < kStageV4) {
+                const int t = idx / kTileV4, within = idx % kTileV4;
+                const int64_t T = static_cast<int64_t>(G) * TPS + t;
+                v4i v = {0, 0, 0, 0};
+                if (T < tiles)
+                    v = within < kFragV4 ? frag[T * kFragV4 + within]
+                                         : cinit[T * 4 + (within - kFragV4)];
+                stage[q] = v;
+            }
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < kPerThread; ++q) {
             const int idx = q * kBlock + threadIdx.x;
-            if (idx < kTileV4) lds[buf * kTileV4 + idx] = stage[q];
+            if (idx < kStageV4) lds[buf * kStageV4 + idx] = stage[q];
         }
     };
 
+    v4i prev[MT];  // accumulators of the previous tile, folded one tile late
+#pragma unroll
+    for (int t = 0; t < MT; ++t) prev[t] = v4i{0, 0, 0, 0};
     fetch(0);
     store(0);
     __syncthreads();
-    for (int T = 0; T < tiles; ++T) {
-        const int cur = T & 1;
-        if (T + 1 < tiles) fetch(T + 1);
-        const v4i c0 = lds[cur * kTileV4 + kFragV4 + grp];
-        v4i a[KS];
+    for (int G = 0; G < groups; ++G) {
+        const int cur = G & 1;
+        if (G + 1 < groups) fetch(G + 1);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) a[s] = lds[cur * kTileV4 + s * 64 + lane];
-        v4i acc[MT];
+        for (int tt = 0; tt < TPS; ++tt) {
+            const v4i* tile = lds + cur * kStageV4 + tt * kTileV4;
+            const v4i c0 = tile[kFragV4 + grp];
+            v4i a[KS];
 #pragma unroll
-        for (int t = 0; t < MT; ++t) acc[t] = c0;
+            for (int s = 0; s < KS; ++s) a[s] = tile[s * 64 + lane];
+            v4i acc[MT];
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+            for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int t = 0; t < MT; ++t)
-                acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], bf[t][s], acc[t], 0, 0, 0);
+                for (int t = 0; t < MT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], bf[t][s],
+                                                                   s == 0 ? c0 : acc[t], 0, 0, 0);
+            fold<MT, COUNT>(prev, acc_out);
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-            if (COUNT)
-                acc_out[t] += nonzeros4(acc[t]);
-            else
-                acc_out[t] = min(acc_out[t], umin4(acc[t]));
+            for (int t = 0; t < MT; ++t) prev[t] = acc[t];
+            // Issue order: the tile's LDS reads, then one fold op after each
+            // matrix product until the fold is done.  The empty asm pins the
+            // fold to this tile (otherwise it sinks to the end of the group and
+            // waits for the last products there).
+            __builtin_amdgcn_sched_group_barrier(0x100, KS + 1, 0);
+#pragma unroll
+            for (int i = 0; i < KS * MT; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                if (i < kFoldValu) __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < MT; ++t) asm volatile("" ::"v"(acc_out[t]));
         }
-        if (T + 1 < tiles) store(cur ^ 1);
+        if (G + 1 < groups) store(cur ^ 1);
         bool leave = false;
-        if (!COUNT && (T % kVoteTiles) == kVoteTiles - 1) {
+        if (!COUNT) {
             bool done = true;
 #pragma unroll
             for (int t = 0; t < MT; ++t) {
-                uint32_t m = acc_out[t];
-                m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16)));
-                m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32)));
-                done = done && (!valid[t] || pre_done[t] || m == 0u);
+                int m = acc_out[t];
+                m = min(m, __shfl_xor(m, 16));
+                m = min(m, __shfl_xor(m, 32));
+                done = done && (!valid[t] || pre_done[t] || m < 0);
             }
             const int wave_done = __all(done) ? 1 : 0;
             if (lane == 0) vote[threadIdx.x >> 6] = wave_done;
@@ -134,6 +193,7 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
         __syncthreads();
         if (leave) break;
     }
+    fold<MT, COUNT>(prev, acc_out);
 }
 
 template <int KS, int MT, bool COUNT>
@@ -142,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     const v4i* __restrict__ low_c, int TL, const v4i* __restrict__ up_frag,
     const v4i* __restrict__ up_c, int TU, uint8_t* __restrict__ flags,
     uint32_t* __restrict__ match) {
-    __shared__ v4i lds[2 * (KS * 64 + 4)];
+    __shared__ v4i lds[2 * tiles_per_stage<KS>() * (KS * 64 + 4)];
     __shared__ int vote[kWaves];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -171,32 +231,33 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
         }
     }
 
-    uint32_t accL[MT], accU[MT];
+    int accL[MT], accU[MT];  // 0 = no match yet in both modes
     bool none[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-        accL[t] = COUNT ? 0u : 0xFFFFFFFFu;
-        accU[t] = COUNT ? 0u : 0xFFFFFFFFu;
+        accL[t] = 0;
+        accU[t] = 0;
         none[t] = false;
     }
     mfma_pass<KS, MT, COUNT>(bf, low_frag, low_c, TL, lds, accL, none, valid, vote);
 
-    // Per-sample lower result across the four lane groups (COUNT: every one of
-    // the 16 TL rows is either a zero or a non-zero accumulator).
+    // Per-sample lower result across the four lane groups (COUNT: matches;
+    // LABEL: negative iff some lower row matched).
     bool lowered[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-        uint32_t m = accL[t];
+        int m = accL[t];
         if (COUNT) {
-            m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16));
-            m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32));
-            m = 16u * static_cast<uint32_t>(TL) - m;
+            uint32_t u = static_cast<uint32_t>(m);
+            u += static_cast<uint32_t>(__shfl_xor(static_cast<int>(u), 16));
+            u += static_cast<uint32_t>(__shfl_xor(static_cast<int>(u), 32));
+            m = static_cast<int>(u >> 3);
         } else {
-            m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16)));
-            m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32)));
+            m = min(m, __shfl_xor(m, 16));
+            m = min(m, __shfl_xor(m, 32));
         }
         accL[t] = m;
-        lowered[t] = COUNT ? false : (m == 0u);
+        lowered[t] = COUNT ? false : (m < 0);
     }
     bool skip_upper = false;
     if (!COUNT) {
@@ -216,14 +277,15 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
 
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-        uint32_t m = accU[t];
+        int m = accU[t];
         if (COUNT) {
-            m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16));
-            m += static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32));
-            m = 16u * static_cast<uint32_t>(TU) - m;
+            uint32_t u = static_cast<uint32_t>(m);
+            u += static_cast<uint32_t>(__shfl_xor(static_cast<int>(u), 16));
+            u += static_cast<uint32_t>(__shfl_xor(static_cast<int>(u), 32));
+            m = static_cast<int>(u >> 3);
         } else {
-            m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 16)));
-            m = min(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32)));
+            m = min(m, __shfl_xor(m, 16));
+            m = min(m, __shfl_xor(m, 32));
         }
         accU[t] = m;
     }
@@ -236,11 +298,11 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
             if (COUNT) {
                 f = static_cast<uint8_t>((accL[t] ? 1 : 0) | (accU[t] ? 2 : 0));
                 if (match) {
-                    match[2 * h] = accL[t];
-                    match[2 * h + 1] = accU[t];
+                    match[2 * h] = static_cast<uint32_t>(accL[t]);
+                    match[2 * h + 1] = static_cast<uint32_t>(accU[t]);
                 }
             } else {
-                f = static_cast<uint8_t>(lowered[t] ? 1 : (accU[t] == 0u ? 2 : 0));
+                f = static_cast<uint8_t>(lowered[t] ? 1 : (accU[t] < 0 ? 2 : 0));
             }
             flags[h] = f;
         }
@@ -250,8 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
 template <int KS>
 hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
                      int mode, uint8_t* flags, uint32_t* match) {
-    // B fragments take MT * KS * 4 VGPRs; at most 120 keeps two waves per SIMD.
-    constexpr int MT = KS >= 30 ? 1 : (30 / KS > 8 ? 8 : 30 / KS);
+    constexpr int MT = sample_tiles<KS>();
     const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
     const dim3 grid(static_cast<unsigned>((N + per_block - 1) / per_block));
     const v4i* lf = reinterpret_cast<const v4i*>(refs->d_lower_frag);

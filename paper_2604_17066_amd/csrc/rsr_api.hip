@@ -338,36 +338,41 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     sort_rows(lo, R_L);
     sort_rows(up, R_U);
 
-    // Matrix-core operands: fragment-ordered 0/1 bytes and accumulator starts.
+    // Matrix-core operands: fragment-ordered bytes and accumulator starts,
+    // chosen so that a row matches exactly when its accumulator is negative.
+    // Lower rows: bytes NOT t(r) in {0, 1}, start -1, so the result is
+    // |t(x) & ~t(r)| - 1.  Upper rows: bytes -t(r) in {0, -1}, start
+    // |t(r)| - 1, so the result is |t(r) & ~t(x)| - 1.  Pad rows and pad
+    // tiles are all zero: result 0, never a match.
     const int KS = (W * 32 + 63) / 64;
     const bool with_mfma = KS <= rsr::kMaxMfmaSteps;
     const int TL = static_cast<int>((R_L + 15) / 16), TU = static_cast<int>((R_U + 15) / 16);
     std::vector<int8_t> lof, upf;
     std::vector<int32_t> loc, upc;
     if (with_mfma) {
-        auto frag = [&](const uint32_t* words, int64_t r, std::vector<int8_t>& dst) {
+        auto frag = [&](const uint32_t* words, int64_t r, int8_t value, std::vector<int8_t>& dst) {
             const int64_t T = r / 16;
             const int rr = static_cast<int>(r % 16);
             for (int k = 0; k < W * 32; ++k) {
                 if (!((words[k / 32] >> (k % 32)) & 1u)) continue;
                 const int s = k / 64, o = k % 64;
                 const int lane = (o / 16) * 16 + rr;
-                dst[((static_cast<size_t>(T) * KS + s) * 64 + lane) * 16 + (o % 16)] = 1;
+                dst[((static_cast<size_t>(T) * KS + s) * 64 + lane) * 16 + (o % 16)] = value;
             }
         };
         lof.assign(static_cast<size_t>(TL) * KS * 1024, 0);
         upf.assign(static_cast<size_t>(TU) * KS * 1024, 0);
-        loc.assign(static_cast<size_t>(TL) * 16, 1);
-        upc.assign(static_cast<size_t>(TU) * 16, 1);
+        loc.assign(static_cast<size_t>(TL) * 16, 0);
+        upc.assign(static_cast<size_t>(TU) * 16, 0);
         for (int64_t r = 0; r < R_L; ++r) {
-            frag(lo.data() + r * WR, r, lof);
-            loc[r] = 0;
+            frag(lo.data() + r * WR, r, 1, lof);
+            loc[r] = -1;
         }
         for (int64_t r = 0; r < R_U; ++r) {
-            frag(up.data() + r * WR, r, upf);
+            frag(up.data() + r * WR, r, -1, upf);
             int pop = 0;
             for (int w = 0; w < W; ++w) pop += __builtin_popcount(up[r * WR + w]);
-            upc[r] = -pop;
+            upc[r] = pop - 1;
         }
     }
 

@@ -65,9 +65,9 @@ struct rsr_refs {
     int KS = 0;                          // 64-wide k-steps: ceil(32 W / 64)
     int TL = 0, TU = 0;                  // 16-row tiles per side
     int8_t* d_lower_frag = nullptr;      // [TL][KS][64 lanes][16]: NOT t(r) as 0/1 bytes
-    int32_t* d_lower_cinit = nullptr;    // [TL * 16]: 0 (row) or 1 (pad row)
-    int8_t* d_upper_frag = nullptr;      // [TU][KS][64][16]: t(r) as 0/1 bytes
-    int32_t* d_upper_cinit = nullptr;    // [TU * 16]: -|t(r)| (row) or 1 (pad row)
+    int32_t* d_lower_cinit = nullptr;    // [TL * 16]: -1 (row) or 0 (pad row)
+    int8_t* d_upper_frag = nullptr;      // [TU][KS][64][16]: -t(r) as 0/-1 bytes
+    int32_t* d_upper_cinit = nullptr;    // [TU * 16]: |t(r)| - 1 (row) or 0 (pad row)
 };
 
 struct rsr_system {
