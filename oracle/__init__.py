@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY: the oracle is a slow, obviously correct CPU
 implementation of what the RSR Stage-2 hot path computes (arXiv 2604.17066,
-sections 2.2, 3.2, 3.3 and 3.5).  Only the tests, the smoke check and the
+sections 2.2, 3.2, 3.3 and 3.5), and of the componentwise boundary search of
+Stage 1 (section 3.4).  Only the tests, the smoke check and the
 CPU-baseline leg of the benchmark may import it.  It shares no code with the
 product package, and it never imports it.
 """
@@ -60,6 +61,11 @@ def _load():
         "bf_reference_sets": (None, [ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int, _u8p, _i64p,
                                      _u8p, _i64p, ctypes.c_int64]),
         "or_state_prob": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _f64p, _u8p]),
+        "or_boundary_table": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int,
+                                               _u8p, ctypes.c_int64, _u8p, _u8p]),
+        "or_boundary_st": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p,
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            _u8p, ctypes.c_int64, _u8p, _u8p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -266,6 +272,34 @@ def reference_sets(table, n, K, level=1, cap=1 << 16):
     if nl.value > cap or nu.value > cap:
         raise ValueError("reference-set buffers too small")
     return lower[: nl.value].copy(), upper[: nu.value].copy()
+
+
+def boundary_table(table, n, K, x, level=1):
+    """Componentwise boundary search (section 3.4) with the system state given
+    as a table over all K^n states.  Returns (states [Ns][n], side [Ns] with
+    0 = lower / 1 = upper reference state, number of system evaluations)."""
+    table = _c(table, np.uint8)
+    x = _c(np.atleast_2d(x), np.uint8)
+    out = np.zeros_like(x)
+    side = np.zeros(x.shape[0], dtype=np.uint8)
+    ev = _load().or_boundary_table(n, K, _ptr(table, ctypes.c_uint8), int(level),
+                                   _ptr(x, ctypes.c_uint8), x.shape[0],
+                                   _ptr(out, ctypes.c_uint8), _ptr(side, ctypes.c_uint8))
+    return out, side, int(ev)
+
+
+def boundary_st(graph, x, K=2, level=1):
+    """Componentwise boundary search for s-t connectivity at `level`."""
+    eu, ev = _graph_args(graph)
+    x = _c(np.atleast_2d(x), np.uint8)
+    out = np.zeros_like(x)
+    side = np.zeros(x.shape[0], dtype=np.uint8)
+    nev = _load().or_boundary_st(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                                 _ptr(ev, ctypes.c_int32), int(graph["source"]),
+                                 int(graph["sink"]), int(level), int(K), _ptr(x, ctypes.c_uint8),
+                                 x.shape[0], _ptr(out, ctypes.c_uint8),
+                                 _ptr(side, ctypes.c_uint8))
+    return out, side, int(nev)
 
 
 def state_prob(p, x):

@@ -272,6 +272,103 @@ int64_t or_eval(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Componentwise boundary search (section 3.4, fig. x1x2_find_ref)            */
+/* ------------------------------------------------------------------------- */
+/* above(x) = 1 when the system state at x reaches the target (S >= level). */
+typedef int (*or_above_fn)(const uint8_t* x, const void* user);
+
+/* One search, in place on x.  When x is below the target (a failure sample),
+ * the components are visited in index order; each is raised one state at a
+ * time while it is below K-1, and a raise that reaches the target is undone,
+ * which ends the visit of that component.  When x reaches the target (a
+ * survival sample) the search is the mirror image: lowering towards 0, and a
+ * lowering that leaves the target is undone.  The result is a maximal failure
+ * state (returns 0, a lower reference state) or a minimal survival state
+ * (returns 1, an upper reference state).  *evals counts calls of above(),
+ * including the first one on the sample itself. */
+static int boundary_search(int n, int K, uint8_t* x, or_above_fn above, const void* user,
+                           int64_t* evals) {
+    int start = above(x, user);
+    int64_t calls = 1;
+    for (int i = 0; i < n; ++i) {
+        if (!start) {
+            while (x[i] < K - 1) {
+                x[i] += 1;
+                calls += 1;
+                if (above(x, user)) {
+                    x[i] -= 1;
+                    break;
+                }
+            }
+        } else {
+            while (x[i] > 0) {
+                x[i] -= 1;
+                calls += 1;
+                if (!above(x, user)) {
+                    x[i] += 1;
+                    break;
+                }
+            }
+        }
+    }
+    if (evals) *evals += calls;
+    return start;
+}
+
+struct table_user {
+    int n, K, level;
+    const uint8_t* table;
+};
+
+static int above_table(const uint8_t* x, const void* user) {
+    const struct table_user* u = (const struct table_user*)user;
+    uint64_t idx = 0;
+    for (int i = u->n - 1; i >= 0; --i) idx = idx * (uint64_t)u->K + x[i];
+    return u->table[idx] >= u->level;
+}
+
+/* Boundary search with the system state given as a table over all K^n states
+ * (digit i of the index in base K is x_i, least significant first).  x: [Ns][n]
+ * start states; out: [Ns][n] boundary states; side: [Ns] 0 lower / 1 upper.
+ * Returns the total number of system-function evaluations. */
+int64_t or_boundary_table(int n, int K, const uint8_t* table, int level, const uint8_t* x,
+                          int64_t Ns, uint8_t* out, uint8_t* side) {
+    struct table_user u = {n, K, level, table};
+    int64_t evals = 0;
+    for (int64_t h = 0; h < Ns; ++h) {
+        memcpy(out + (size_t)h * n, x + (size_t)h * n, (size_t)n);
+        side[h] = (uint8_t)boundary_search(n, K, out + (size_t)h * n, above_table, &u, &evals);
+    }
+    return evals;
+}
+
+struct st_user {
+    int n_nodes, n_edges, s, t, level;
+    const int32_t *eu, *ev;
+};
+
+static int above_st(const uint8_t* x, const void* user) {
+    const struct st_user* u = (const struct st_user*)user;
+    return or_phi_st(u->n_nodes, u->n_edges, u->eu, u->ev, u->s, u->t, u->level, x);
+}
+
+/* Boundary search for s-t connectivity at `level` (components = edges). */
+int64_t or_boundary_st(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int s,
+                       int t, int level, int K, const uint8_t* x, int64_t Ns, uint8_t* out,
+                       uint8_t* side) {
+    struct st_user u = {n_nodes, n_edges, s, t, level, eu, ev};
+    int64_t evals = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : evals)
+    for (int64_t h = 0; h < Ns; ++h) {
+        int64_t e = 0;
+        memcpy(out + (size_t)h * n_edges, x + (size_t)h * n_edges, (size_t)n_edges);
+        side[h] = (uint8_t)boundary_search(n_edges, K, out + (size_t)h * n_edges, above_st, &u, &e);
+        evals += e;
+    }
+    return evals;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Estimators (section 3.3.1)                                                 */
 /* ------------------------------------------------------------------------- */
 /* counts: [0] n_L = #{lower}, [1] n_U = #{upper and not lower},

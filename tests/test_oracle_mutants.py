@@ -2,8 +2,8 @@
 
 Each mutant is a copy of oracle/oracle.c with one plausible mistake planted
 (a swapped constant, an off-by-one, a flipped comparison, a dropped term, a
-wrong index).  It is compiled to a temporary library and the pin suite
-(test_oracle_pins.py) runs against it in a subprocess; every mutant must make
+wrong index).  It is compiled to a temporary library and the pin suites
+(test_oracle_pins.py, test_oracle_boundary.py) run against it in a subprocess; every mutant must make
 at least one pin fail.  This shows that the pins constrain every part of the
 oracle, not only that the oracle passes them."""
 import concurrent.futures as cf
@@ -48,7 +48,13 @@ MUTANTS = {
     "paper encoding: down-set strict": ("(m <= (int)r[i] ? 1 : 0)", "(m < (int)r[i] ? 1 : 0)"),
     "counts: both-flag samples counted upper": ("if (lo) nL += 1;\n        else if (up) nU += 1;",
                                                "if (lo && !up) nL += 1;\n        else if (up) nU += 1;"),
+    "boundary: crossing raise kept": ("x[i] -= 1;\n                    break;", "break;"),
+    "boundary: crossing lowering kept": ("x[i] += 1;\n                    break;", "break;"),
+    "boundary: components visited in reverse": ("for (int i = 0; i < n; ++i) {\n        if (!start) {",
+                                                "for (int i = n - 1; i >= 0; --i) {\n        if (!start) {"),
+    "boundary: sides swapped": ("        if (!start) {\n            while", "        if (start) {\n            while"),
 }
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_boundary.py"]
 
 
 def _run(name, old, new, tmp):
@@ -60,7 +66,8 @@ def _run(name, old, new, tmp):
     subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                     "-o", path_so, path_c, "-lm"], check=True, capture_output=True)
     env = dict(os.environ, RSR_ORACLE_LIB=path_so, OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+    r = subprocess.run([sys.executable, "-m", "pytest",
+                        *[os.path.join(ROOT, "tests", f) for f in PIN_FILES],
                         "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, r.returncode

@@ -101,7 +101,8 @@ def test_sample_ranges_and_threads_agree():
 def _golden_worked():
     lines = [ln.strip() for ln in open(os.path.join(GOLDEN, "worked_example_2x5.txt"))
              if ln.strip() and not ln.startswith("#")]
-    data = {"lower": [], "upper": [], "sample": [], "unclassified": [], "matrix": {}}
+    data = {"lower": [], "upper": [], "sample": [], "unclassified": [], "matrix": {},
+            "phi_zero": [], "phi_one": [], "boundary_from": [], "boundary_result": []}
     k = 0
     while k < len(lines):
         tok = lines[k].split()
