@@ -33,7 +33,7 @@ MFMA_I8_PEAK_OPS = 5.0e15
 # changes, until the counters are taken again.
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
-    "mfma": None,  # counters not yet retaken for the current kernel
+    "mfma": (433.90 + 0.95) * 2 ** 20,
 }
 
 

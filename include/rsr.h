@@ -11,7 +11,8 @@
  *                     (section 3.5, Stage 2)
  *   rsr_estimate      reduce labels to probability estimates (section 3.3.1)
  *   rsr_grad          score-function partials dP/dp[i][s]
- * plus handles for the problem data (component-state probabilities,
+ * and, for Stage 1, rsr_boundary_search (new reference states from
+ * unclassified samples, section 3.4), plus handles for the problem data (component-state probabilities,
  * reference states, system function) and a batched plan that runs many
  * (model, system) jobs in one captured HIP graph.
  *
@@ -213,6 +214,29 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
  * d_samples must hold the samples of `model` that produced d_Y. */
 rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
                     const uint8_t* d_Y, int64_t N, float* d_G, uint64_t* d_counts);
+
+/* ---- Stage 1: new reference states -------------------------------------- */
+
+/* Componentwise boundary search (section 3.4, fig. x1x2_find_ref) from the
+ * samples d_pick[0..n_pick-1] (device i64 indices into the N samples of
+ * d_samples, drawn for a model with the system's n and K).  For each start
+ * x the components are visited in index order; each is moved one state at a
+ * time towards K-1 when Phi(x) says S < level (a failure sample), or towards
+ * 0 when S >= level (a survival sample), and the step that changes the side
+ * is undone, which ends that component's walk.  The result is a maximal
+ * failure state (a new lower reference state) or a minimal survival state
+ * (a new upper one):
+ *   d_rows  device [n_pick][n] u8: the boundary state of pick j in row j
+ *   d_side  device [n_pick] u8:   0 lower, 1 upper, 0xFF if d_pick[j] is not
+ *                                 in 0..N-1 (row j is then left untouched).
+ * For s-t connectivity at a level the side depends only on which edges reach
+ * the level, so a failure result holds every edge at K-1 or level-1 and a
+ * survival result at level or 0.  Rows from different picks may coincide.
+ * EINVAL: NULL argument, N out of 1..2^31-1, n_pick < 0.  n_pick = 0 is a
+ * no-op. */
+rsr_status rsr_boundary_search(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples,
+                               int64_t N, const int64_t* d_pick, int64_t n_pick,
+                               uint8_t* d_rows, uint8_t* d_side);
 
 /* ---- batched plan -------------------------------------------------------- */
 

@@ -69,6 +69,7 @@ SIGNATURES = {
     "rsr_eval_unknown": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]),
     "rsr_estimate": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(rsr_estimate_t)]),
     "rsr_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "rsr_boundary_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "rsr_plan_create": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_job), _i32, _i32, _pp]),
     "rsr_plan_run": (ctypes.c_int, [_vp]),
     "rsr_plan_results": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_estimate_t), _vp]),

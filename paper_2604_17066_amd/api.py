@@ -188,6 +188,19 @@ def rsr_grad(ctx, model, samples, Y, N, G=None, counts=None, want_counts=False):
     return (G, counts) if want_counts else G
 
 
+def rsr_boundary_search(ctx, system, samples, N, picks, rows=None, side=None):
+    """Boundary states from the samples picks (device int64 indices): returns
+    (rows [n_pick][n] u8, side [n_pick] u8: 0 lower, 1 upper)."""
+    n_pick = int(picks.numel())
+    if rows is None:
+        rows = torch.empty((n_pick, system.n), dtype=torch.uint8, device=ctx.device)
+    if side is None:
+        side = torch.empty(n_pick, dtype=torch.uint8, device=ctx.device)
+    ctx.check(A.lib().rsr_boundary_search(ctx.h, system.h, _ptr(samples), int(N), _ptr(picks),
+                                          n_pick, _ptr(rows), _ptr(side)))
+    return rows, side
+
+
 class Buffers:
     """Device buffers for one Stage-2 pass of N samples of an n x K model."""
 

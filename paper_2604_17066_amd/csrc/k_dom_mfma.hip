@@ -68,21 +68,25 @@ __device__ __forceinline__ void fold(const v4i (&r)[MT], int (&acc_out)[MT]) {
     }
 }
 
-// Reference tiles staged per barrier: keeps the double-buffered LDS stage at
-// 2 * TPS * KS KB (at most 40 KB) and gives the global loads of the next group
-// TPS tiles of matrix work to land.  (Four tiles per stage makes the compiler
-// hold more than one tile's operands and spill.)
+// Reference tiles staged per barrier.  One block fills a CU (two waves per
+// SIMD), so the barrier at the end of a group idles the whole CU; large groups
+// make that rare and give the global loads of the next group a whole group of
+// matrix work to land.  The double-buffered stage takes 2 * TPS * (KS KB +
+// 64 B) of LDS, at most 83 KB.
 template <int KS>
 constexpr int tiles_per_stage() {
-    return KS <= 10 ? 2 : 1;
+    return KS <= 5 ? 8 : (KS <= 10 ? 4 : 2);
 }
 
 // Sample tiles per wave: B fragments take MT * KS * 4 VGPRs, and with the two
 // accumulator sets of the pipelined fold everything must fit 256 VGPRs (two
-// waves per SIMD) without spilling.
+// waves per SIMD) without spilling.  For KS = 5 (up to 320 bits, the 295-edge
+// workloads) four tiles measure faster than five: a block then covers 512
+// samples, and 10^6 samples make 7.6 rounds of blocks over 256 CUs instead of
+// 6.1, so the last, partly idle round costs less.
 template <int KS>
 constexpr int sample_tiles() {
-    return KS <= 2 ? 8 : KS == 3 ? 7 : KS == 4 ? 6 : KS == 5 ? 5 : (KS >= 30 ? 1 : 30 / KS);
+    return KS <= 2 ? 8 : KS == 3 ? 7 : KS == 4 ? 6 : KS == 5 ? 4 : (KS >= 30 ? 1 : 30 / KS);
 }
 
 // One pass over the tiles of one side.  acc_out[t] = 8 * matches (COUNT) or
@@ -102,7 +106,6 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
     constexpr int TPS = tiles_per_stage<KS>();
     constexpr int kStageV4 = TPS * kTileV4;
     constexpr int kPerThread = (kStageV4 + kBlock - 1) / kBlock;
-    constexpr int kFoldValu = COUNT ? 4 * MT : 2 * MT;
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4;
     if (tiles <= 0) return;
@@ -158,16 +161,8 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
             fold<MT, COUNT>(prev, acc_out);
 #pragma unroll
             for (int t = 0; t < MT; ++t) prev[t] = acc[t];
-            // Issue order: the tile's LDS reads, then one fold op after each
-            // matrix product until the fold is done.  The empty asm pins the
-            // fold to this tile (otherwise it sinks to the end of the group and
-            // waits for the last products there).
-            __builtin_amdgcn_sched_group_barrier(0x100, KS + 1, 0);
-#pragma unroll
-            for (int i = 0; i < KS * MT; ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                if (i < kFoldValu) __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
-            }
+            // The empty asm pins the fold to this tile: otherwise it sinks to
+            // the end of the group and waits there for the last products.
 #pragma unroll
             for (int t = 0; t < MT; ++t) asm volatile("" ::"v"(acc_out[t]));
         }

@@ -558,6 +558,23 @@ rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t*
     return RSR_OK;
 }
 
+rsr_status rsr_boundary_search(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples,
+                               int64_t N, const int64_t* d_pick, int64_t n_pick,
+                               uint8_t* d_rows, uint8_t* d_side) {
+    if (!ctx) return RSR_EINVAL;
+    if (n_pick < 0) return fail(ctx, RSR_EINVAL, "n_pick must be >= 0");
+    if (n_pick == 0) return RSR_OK;
+    if (!sys || !d_samples || !d_pick || !d_rows || !d_side)
+        return fail(ctx, RSR_EINVAL, "NULL argument");
+    if (N <= 0 || N > 0x7FFFFFFFll) return fail(ctx, RSR_EINVAL, "N must be in 1..2^31-1");
+    if (rsr::boundary_lds_bytes(sys->n_nodes, sys->n_edges) > 64 * 1024)
+        return fail(ctx, RSR_EUNSUPPORTED, "graph too large for the boundary search");
+    DeviceGuard g(ctx->device);
+    RSR_HIP(ctx, rsr::launch_boundary(ctx->stream, sys, d_samples, N, d_pick, n_pick, d_rows,
+                                      d_side, ctx->cu_count * 8));
+    return RSR_OK;
+}
+
 rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
                         rsr_estimate_t* out) {
     if (!ctx) return RSR_EINVAL;

@@ -185,6 +185,10 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
                       const int32_t* d_list, const uint64_t* d_count, int which,
                       uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
+size_t boundary_lds_bytes(int n_nodes, int n_edges);
+hipError_t launch_boundary(hipStream_t st, const rsr_system* sys, const uint32_t* xs, int64_t N,
+                           const int64_t* d_pick, int64_t n_pick, uint8_t* d_rows,
+                           uint8_t* d_side, int grid_cap);
 // With a job table (jobs != nullptr) the reductions run once per job in one
 // launch; N must then be the largest job size (it sizes the grid), counters
 // receive [n_jobs][8] and the gradient partials need n_jobs * (W * bx * 32 +
