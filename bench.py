@@ -168,6 +168,7 @@ def main():
         extra["scaling_count_mode"] = scaling_leg(ctx, reps)
         extra["multi_state"] = multi_leg(ctx, reps)
         extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps)
+        extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
 
     out = {
         "metric": "dominance tests/s (samples x reference states), whole Stage-2 step",
@@ -296,6 +297,48 @@ def multi_leg(ctx, reps):
     return res
 
 
+def stage1_leg(ctx, with_cpu):
+    """Stage 1 on graph2 from empty reference sets (section 3.5): 1e5 samples
+    per iteration, 1024 boundary searches per iteration, until p_u < 1e-3 or
+    2e4 rows or 100 iterations; plus the boundary search alone on 2^17 start
+    samples, and (with_cpu) the oracle's search on 256 of them as its CPU
+    baseline."""
+    import time as _t
+    import torch
+    import paper_2604_17066_amd as R
+    import workloads as WL
+    cfg = WL.configs.graph2(N=1, R_U=10, R_L=10)
+    model = R.Model(ctx, cfg["p"])
+    system = R.System(ctx, cfg["graph"])
+    R.stage1(ctx, model, system, 10_000, 64, 1e-3, 200, 3, 1)   # warm-up
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    lo, up, info = R.stage1(ctx, model, system, 100_000, 1024, 1e-3, 20_000, 100, 5)
+    loop_s = _t.perf_counter() - t0
+    N = 1 << 17
+    xs = R.rsr_sample(ctx, model, 9, 0, 0, N)
+    picks = torch.arange(0, N, dtype=torch.int64, device=ctx.device)
+    rows, side = R.rsr_boundary_search(ctx, system, xs, N, picks)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(5):
+        R.rsr_boundary_search(ctx, system, xs, N, picks, rows=rows, side=side)
+    e1.record(st)
+    torch.cuda.synchronize()
+    search_ms = e0.elapsed_time(e1) / 5
+    out = {"workload": "graph2 (295 edges) from empty reference sets; 1e5 samples and 1024 searches "
+                       "per iteration; stop at p_u < 1e-3, 2e4 rows or 100 iterations",
+           "loop_s": loop_s, **info, "rows": int(info["R_L"] + info["R_U"]),
+           "boundary_searches_per_s": N / (search_ms * 1e-3), "boundary_search_ms_2e17": search_ms}
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline_boundary(cfg, 9, 256)
+    log(f"stage 1: {info['iterations']} iterations, {out['rows']} rows, p_u {info['p_u']:.2e}, "
+        f"{loop_s:.2f} s; boundary search {out['boundary_searches_per_s']:.3g}/s")
+    return out
+
+
 def batched_leg(ctx, ref_scale, reps):
     """64 hazard scenarios x 8 graphs = 512 jobs at N = 2^18 (SE <= 1e-3 for any
     P): the batched plan (one graph launch) against the plain form (the
@@ -356,6 +399,19 @@ def batched_leg(ctx, ref_scale, reps):
             "plain_ms": plain_ms, "batched_ms": batched_ms, "speedup": plain_ms / batched_ms,
             "plan_create_s": create_s, "identical_estimates": same, "max_se": se,
             "nominal_tests_per_s_batched": total_tests / (batched_ms * 1e-3)}
+
+
+def cpu_baseline_boundary(cfg, seed, count):
+    """The oracle's componentwise boundary search (one system evaluation per
+    single step) from the first `count` samples of the same model and seed as
+    the GPU timing, on the host cores."""
+    import oracle
+    x = oracle.sample(cfg["p"], seed, 0, 0, count)
+    t = time.perf_counter()
+    oracle.boundary_st(cfg["graph"], x)
+    dt = time.perf_counter() - t
+    return {"value": count / dt, "unit": "boundary searches/s", "cores": oracle.get_threads(),
+            "kind": "oracle", "sample": f"{count} start samples of graph2, {dt:.2f} s"}
 
 
 def cpu_baseline(cfg, R_total, seconds):

@@ -12,7 +12,8 @@
  *   rsr_estimate      reduce labels to probability estimates (section 3.3.1)
  *   rsr_grad          score-function partials dP/dp[i][s]
  * and, for Stage 1, rsr_boundary_search (new reference states from
- * unclassified samples, section 3.4), plus handles for the problem data (component-state probabilities,
+ * unclassified samples, section 3.4) and the loop around it, rsr_stage1,
+ * plus handles for the problem data (component-state probabilities,
  * reference states, system function) and a batched plan that runs many
  * (model, system) jobs in one captured HIP graph.
  *
@@ -237,6 +238,48 @@ rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samp
 rsr_status rsr_boundary_search(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples,
                                int64_t N, const int64_t* d_pick, int64_t n_pick,
                                uint8_t* d_rows, uint8_t* d_side);
+
+/* Stage 1 of the workflow (section 3.5, Stage 1 of fig. rsr_alg): alternate
+ * sample classification and boundary search until the unclassified fraction
+ * of a fresh sample set falls below eps_u or the reference sets reach
+ * max_rows rows.  Iteration it (0, 1, ...):
+ *   1. draw N samples with key `seed` and stream_id = it (rsr_sample);
+ *   2. classify them against the current rows in LABEL mode;
+ *   3. p_u = (unclassified samples) / N; stop if p_u < eps_u, if the rows
+ *      number max_rows or more, or if it + 1 = max_iters;
+ *   4. search from the first `picks` unclassified samples in index order
+ *      (the paper picks one at random per iteration; samples are i.i.d., so
+ *      the lowest-index ones are a uniformly random subset, and picks > 1
+ *      finds that many rows per sample set);
+ *   5. append each new row to its side in pick order, dropping rows already
+ *      present and stopping at max_rows rows in total.
+ * A row found from an unclassified sample is never dominated by an existing
+ * row of a valid reference set (the sample would have been classified), so
+ * exact duplicates are the only redundancy to remove.  Rows are host
+ * [R][n] u8, in discovery order after the initial rows (lower0 / upper0,
+ * which may be NULL with R = 0).  lower / upper must hold cap_L / cap_U rows;
+ * both must be at least max_rows.  Synchronous. */
+typedef struct {
+    int64_t N;          /* samples per iteration, 1..2^31-1 */
+    int64_t picks;      /* unclassified samples searched per iteration, >= 1 */
+    double eps_u;       /* target unclassified fraction */
+    int64_t max_rows;   /* cap on R_L + R_U */
+    int32_t max_iters;  /* cap on iterations, >= 1 */
+    uint64_t seed;
+} rsr_stage1_params;
+
+typedef struct {
+    int32_t iterations;  /* sample sets drawn and classified */
+    double p_u;          /* unclassified fraction of the last sample set */
+    int64_t R_L, R_U;    /* rows returned */
+    int64_t searches;    /* boundary searches run */
+    int64_t duplicates;  /* search results dropped as already present */
+} rsr_stage1_result;
+
+rsr_status rsr_stage1(rsr_ctx* ctx, const rsr_model* model, const rsr_system* sys,
+                      const rsr_stage1_params* params, const uint8_t* lower0, int64_t R_L0,
+                      const uint8_t* upper0, int64_t R_U0, uint8_t* lower, int64_t cap_L,
+                      uint8_t* upper, int64_t cap_U, rsr_stage1_result* result);
 
 /* ---- batched plan -------------------------------------------------------- */
 

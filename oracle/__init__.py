@@ -302,6 +302,51 @@ def boundary_st(graph, x, K=2, level=1):
     return out, side, int(nev)
 
 
+def stage1(graph, p, N, picks, eps_u, max_rows, max_iters, seed, K=2, level=1, lower0=None,
+           upper0=None):
+    """The Stage-1 loop (section 3.5, fig. rsr_alg), written with the plain
+    functions above.  Iteration it draws N samples (key seed, stream it),
+    classifies them against the current rows (Algorithm 1), and stops when the
+    unclassified fraction p_u is below eps_u, the rows number max_rows, or it
+    is the last iteration; otherwise it searches from the first `picks`
+    unclassified samples in index order (section 3.4) and appends each result
+    not already present, in pick order, up to max_rows rows in total.
+    Returns (lower rows, upper rows, dict of iterations, p_u, searches,
+    duplicates)."""
+    n = np.asarray(p).shape[0]
+    rows = [list(map(bytes, np.zeros((0, n), np.uint8) if lower0 is None else np.asarray(lower0, np.uint8))),
+            list(map(bytes, np.zeros((0, n), np.uint8) if upper0 is None else np.asarray(upper0, np.uint8)))]
+    seen = [set(rows[0]), set(rows[1])]
+    info = {"iterations": 0, "p_u": 1.0, "searches": 0, "duplicates": 0}
+    for it in range(max_iters):
+        x = sample(p, seed, it, 0, N)
+        as_arr = [np.frombuffer(b"".join(r), np.uint8).reshape(-1, n) for r in rows]
+        flags, _, _ = classify(as_arr[0], as_arr[1], x, mode=0)
+        unknown = np.nonzero((flags & 3) == 0)[0]
+        info["iterations"] = it + 1
+        info["p_u"] = unknown.size / N
+        total = len(rows[0]) + len(rows[1])
+        if info["p_u"] < eps_u or total >= max_rows or it + 1 == max_iters:
+            break
+        chosen = unknown[:picks]
+        if chosen.size == 0:
+            break
+        out, side, _ = boundary_st(graph, x[chosen], K=K, level=level)
+        info["searches"] += chosen.size
+        for r, sd in zip(out, side):
+            if total >= max_rows:
+                break
+            key = bytes(r)
+            if key in seen[sd]:
+                info["duplicates"] += 1
+                continue
+            seen[sd].add(key)
+            rows[sd].append(key)
+            total += 1
+    lo, up = (np.frombuffer(b"".join(r), np.uint8).reshape(-1, n).copy() for r in rows)
+    return lo, up, info
+
+
 def state_prob(p, x):
     p = _c(p, np.float64)
     n, K = p.shape

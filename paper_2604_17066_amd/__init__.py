@@ -11,6 +11,6 @@ from ._abi import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Context, Model, Refs, System, Buffers, Plan, alloc_samples, rsr_sample, rsr_classify,
-    rsr_eval_unknown, rsr_estimate, rsr_grad, rsr_boundary_search, stage2,
+    rsr_eval_unknown, rsr_estimate, rsr_grad, rsr_boundary_search, stage1, stage2,
 )
 from .autograd import RSRProbability, rsr_probability  # noqa: F401

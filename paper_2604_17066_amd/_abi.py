@@ -46,6 +46,21 @@ class rsr_job(ctypes.Structure):
                 ("d_Y", ctypes.c_void_p), ("d_G", ctypes.c_void_p)]
 
 
+class rsr_stage1_params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("picks", ctypes.c_int64), ("eps_u", ctypes.c_double),
+                ("max_rows", ctypes.c_int64), ("max_iters", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class rsr_stage1_result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("p_u", ctypes.c_double), ("R_L", ctypes.c_int64),
+                ("R_U", ctypes.c_int64), ("searches", ctypes.c_int64),
+                ("duplicates", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _pp = ctypes.POINTER(ctypes.c_void_p)
 _i32, _i64, _u32, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
@@ -70,6 +85,8 @@ SIGNATURES = {
     "rsr_estimate": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(rsr_estimate_t)]),
     "rsr_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "rsr_boundary_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "rsr_stage1": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                  _i64, _vp]),
     "rsr_plan_create": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_job), _i32, _i32, _pp]),
     "rsr_plan_run": (ctypes.c_int, [_vp]),
     "rsr_plan_results": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_estimate_t), _vp]),

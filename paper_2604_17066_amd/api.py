@@ -201,6 +201,34 @@ def rsr_boundary_search(ctx, system, samples, N, picks, rows=None, side=None):
     return rows, side
 
 
+def stage1(ctx, model, system, N, picks, eps_u, max_rows, max_iters, seed, lower0=None,
+           upper0=None):
+    """Stage-1 loop (rsr_stage1): returns (lower rows, upper rows, result dict),
+    rows as uint8 numpy arrays [R][n] in discovery order."""
+    n = model.n
+
+    def rows(a):
+        if a is None:
+            return np.zeros((0, n), dtype=np.uint8)
+        return np.ascontiguousarray(a, dtype=np.uint8).reshape(-1, n)
+
+    lo0, up0 = rows(lower0), rows(upper0)
+    cap_l = max(int(max_rows), lo0.shape[0])
+    cap_u = max(int(max_rows), up0.shape[0])
+    lower = np.zeros((cap_l, n), dtype=np.uint8)
+    upper = np.zeros((cap_u, n), dtype=np.uint8)
+    prm = A.rsr_stage1_params(int(N), int(picks), float(eps_u), int(max_rows), int(max_iters),
+                              int(seed))
+    res = A.rsr_stage1_result()
+    ctx.check(A.lib().rsr_stage1(ctx.h, model.h, system.h, ctypes.byref(prm),
+                                 lo0.ctypes.data if lo0.size else None, lo0.shape[0],
+                                 up0.ctypes.data if up0.size else None, up0.shape[0],
+                                 lower.ctypes.data, cap_l, upper.ctypes.data, cap_u,
+                                 ctypes.byref(res)))
+    out = res.as_dict()
+    return lower[: out["R_L"]].copy(), upper[: out["R_U"]].copy(), out
+
+
 class Buffers:
     """Device buffers for one Stage-2 pass of N samples of an n x K model."""
 

@@ -186,6 +186,10 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
                       uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
 size_t boundary_lds_bytes(int n_nodes, int n_edges);
+// First B unclassified samples in index order -> d_pick; *d_total = all of
+// them.  d_part: at least 1024 u64 of scratch.
+hipError_t launch_pick(hipStream_t st, const uint8_t* d_flags, int64_t N, int64_t B,
+                       int64_t* d_pick, uint64_t* d_part, uint64_t* d_total);
 hipError_t launch_boundary(hipStream_t st, const rsr_system* sys, const uint32_t* xs, int64_t N,
                            const int64_t* d_pick, int64_t n_pick, uint8_t* d_rows,
                            uint8_t* d_side, int grid_cap);

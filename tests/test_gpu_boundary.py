@@ -91,3 +91,36 @@ def test_boundary_pick_edge_cases(rsr_ctx):
     np.testing.assert_array_equal(s[[0, 4]], want_side)
     with pytest.raises(R.RSRError):
         R.rsr_boundary_search(rsr_ctx, system, xs, 0, picks)
+
+
+@pytest.mark.parametrize("case", ["tiny", "graph2", "multi"])
+def test_stage1_loop_matches_oracle(rsr_ctx, case):
+    """rsr_stage1 against the oracle's loop: the same rows in the same order,
+    the same iteration count, unclassified fraction, searches and
+    duplicates."""
+    K, level, lower0, upper0 = 2, 1, None, None
+    if case == "tiny":
+        c = WL.configs.tiny(N=10)
+        graph, p = c["graph"], WL.configs.binary_model(c["p"][:, 1] * 0.9)
+        N, picks, iters, max_rows = 3000, 16, 40, 10_000
+    elif case == "graph2":
+        c = WL.configs.graph2(N=1, R_U=40, R_L=40)
+        graph, p = c["graph"], c["p"]
+        N, picks, iters, max_rows = 20_000, 64, 4, 10_000
+        lower0, upper0 = c["lower"], c["upper"]      # start from given rows
+    else:
+        c = WL.configs.multi(N=1, R_per_level=4)
+        graph, p, K, level = c["graph"], c["p"], 3, 2
+        N, picks, iters, max_rows = 10_000, 32, 3, 70
+    m = R.Model(rsr_ctx, p)
+    system = R.System(rsr_ctx, graph, K=K, level=level)
+    lo, up, info = R.stage1(rsr_ctx, m, system, N, picks, 1e-9, max_rows, iters, 17,
+                            lower0=lower0, upper0=upper0)
+    wlo, wup, winfo = oracle.stage1(graph, p, N, picks, 1e-9, max_rows, iters, 17, K=K,
+                                    level=level, lower0=lower0, upper0=upper0)
+    print(case, info)
+    for key in ("iterations", "p_u", "searches", "duplicates"):
+        assert info[key] == winfo[key], key
+    np.testing.assert_array_equal(lo, wlo)
+    np.testing.assert_array_equal(up, wup)
+    assert info["searches"] > 0

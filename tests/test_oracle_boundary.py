@@ -121,3 +121,35 @@ def test_multistate_levels_on_the_bridge():
             else:
                 assert bytes(out[h]) in lo_set
                 assert set(out[h].tolist()) <= {level - 1, K - 1}
+
+
+def test_stage1_loop_on_tiny():
+    """The oracle's Stage-1 loop from empty reference sets on the 20-edge
+    graph: every row it finds is a brute-force boundary state of its side,
+    the sets grow until a fresh sample set has no unclassified sample, and
+    picks = 1 (the paper's one search per iteration) finds one new row per
+    iteration until then."""
+    c = WL.configs.tiny(N=10)
+    n = c["n"]
+    table = oracle.phi_table_st(c["graph"])
+    lo_all, up_all = oracle.reference_sets(table, n, 2)
+    lo_set, up_set = set(map(bytes, lo_all)), set(map(bytes, up_all))
+    p = WL.configs.binary_model(c["p"][:, 1] * 0.9)
+    lo, up, info = oracle.stage1(c["graph"], p, N=3000, picks=16, eps_u=1e-9, max_rows=10_000,
+                                 max_iters=60, seed=3)
+    assert info["p_u"] == 0.0 and info["iterations"] < 60
+    assert len(lo) + len(up) + info["duplicates"] == info["searches"]
+    assert set(map(bytes, lo)) <= lo_set and set(map(bytes, up)) <= up_set
+    assert len(set(map(bytes, lo))) == len(lo) and len(set(map(bytes, up))) == len(up)
+    # The grown sets are valid: no state is labelled against its Phi.
+    idx = np.arange(1 << n, dtype=np.uint64)
+    states = ((idx[:, None] >> np.arange(n, dtype=np.uint64)) & np.uint64(1)).astype(np.uint8)
+    flags, _, _ = oracle.classify(lo, up, states, mode=1)
+    assert not np.any((flags & 1) & (table == 1)) and not np.any((flags & 2) & (table == 0))
+    lo1, up1, info1 = oracle.stage1(c["graph"], p, N=3000, picks=1, eps_u=1e-9, max_rows=10_000,
+                                    max_iters=8, seed=3)
+    assert info1["searches"] == 7 and info1["duplicates"] == 0 and len(lo1) + len(up1) == 7
+    # max_rows caps the total, and the loop stops once it is reached.
+    lo2, up2, info2 = oracle.stage1(c["graph"], p, N=3000, picks=16, eps_u=0.0, max_rows=5,
+                                    max_iters=60, seed=3)
+    assert len(lo2) + len(up2) == 5 and info2["iterations"] == 2
