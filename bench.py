@@ -27,13 +27,16 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # MI355X dense int8 matrix-core peak (AMD's published figure, no sparsity).
 MFMA_I8_PEAK_OPS = 5.0e15
+# MI355X dense FP4 (and FP6) matrix-core peak, flops.
+MFMA_FP4_PEAK_FLOPS = 10.1e15
 # HBM bytes per launch of the COUNT-mode classification on the graph2 workload,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
 # (profiles/bench_graph2_hbm_traffic.md).  Set an entry to None when its kernel
 # changes, until the counters are taken again.
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
-    "mfma": (433.90 + 0.95) * 2 ** 20,
+    "mfma": None,
+    "mfma_fp4": None,
 }
 
 
@@ -49,7 +52,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", default="popcount", choices=["auto", "popcount", "mfma"])
+    ap.add_argument("--form", default="popcount", choices=["auto", "popcount", "mfma", "mfma_fp4"])
     ap.add_argument("--skip-legs", action="store_true",
                     help="only the graph2 step (no scaling / multi-state / batched legs)")
     ap.add_argument("--batched-scale", type=float, default=0.25,
@@ -79,7 +82,8 @@ def main():
     import paper_2604_17066_amd as R
     import workloads as WL
 
-    form = {"auto": R.RSR_AUTO, "popcount": R.RSR_POPCOUNT, "mfma": R.RSR_MFMA}[args.form]
+    form = {"auto": R.RSR_AUTO, "popcount": R.RSR_POPCOUNT, "mfma": R.RSR_MFMA,
+            "mfma_fp4": R.RSR_MFMA_FP4}[args.form]
     t0 = time.time()
     cfg = WL.configs.graph2()
     N, n, K = cfg["N"], cfg["n"], cfg["K"]
@@ -140,8 +144,10 @@ def main():
 
     W = model.words
     KP = 64 * ((32 * W + 63) // 64)
+    KP4 = 128 * ((32 * W + 127) // 128)
     kern = {}
-    for fname, f in (("popcount", R.RSR_POPCOUNT), ("mfma", R.RSR_MFMA)):
+    for fname, f in (("popcount", R.RSR_POPCOUNT), ("mfma", R.RSR_MFMA),
+                     ("mfma_fp4", R.RSR_MFMA_FP4)):
         kern[fname] = {"count_ms": time_classify(R.RSR_COUNT, f),
                        "label_ms": time_classify(R.RSR_LABEL, f)}
     # Popcount form: one 32-bit AND-OR per packed word per test on the vector ALU.
@@ -150,9 +156,14 @@ def main():
     # Matrix-core form: 2 KP int8 operations per test (KP = packed bits rounded to 64).
     kern["mfma"]["count_achieved"] = float(tests) * 2 * KP / (kern["mfma"]["count_ms"] * 1e-3)
     kern["mfma"]["count_frac"] = kern["mfma"]["count_achieved"] / MFMA_I8_PEAK_OPS
+    # FP4 form: 2 KP4 flops per test (KP4 = packed bits rounded to 128), dense FP4 peak.
+    kern["mfma_fp4"]["count_achieved"] = float(tests) * 2 * KP4 / (kern["mfma_fp4"]["count_ms"] * 1e-3)
+    kern["mfma_fp4"]["count_frac"] = kern["mfma_fp4"]["count_achieved"] / MFMA_FP4_PEAK_FLOPS
     for k, v in kern.items():
         log(f"{k}: COUNT {v['count_ms']:.3f} ms ({v['count_frac'] * 100:.1f}% of peak), "
             f"LABEL {v['label_ms']:.3f} ms")
+    peaks = {"popcount": VALU_PEAK_OPS, "mfma": MFMA_I8_PEAK_OPS, "mfma_fp4": MFMA_FP4_PEAK_FLOPS}
+    ops_per_test = {"popcount": W, "mfma": 2 * KP, "mfma_fp4": 2 * KP4}
     dom = args.form if args.form != "auto" else "popcount"
     count_ms = kern[dom]["count_ms"]
     achieved = kern[dom]["count_achieved"]
@@ -195,13 +206,13 @@ def main():
             "kernel": f"rsr_classify {dom} form, COUNT mode (every test in full), same workload",
             "bound": "alu" if dom == "popcount" else "mfma",
             "achieved": achieved / 1e12,
-            "peak": (VALU_PEAK_OPS if dom == "popcount" else MFMA_I8_PEAK_OPS) / 1e12,
-            "unit": "TOP/s",
-            "frac": achieved / (VALU_PEAK_OPS if dom == "popcount" else MFMA_I8_PEAK_OPS),
+            "peak": peaks[dom] / 1e12,
+            "unit": "TFLOP/s" if dom == "mfma_fp4" else "TOP/s",
+            "frac": achieved / peaks[dom],
             "traffic": COUNT_TRAFFIC_BYTES.get(dom),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "algorithmic_bytes": 4.0 * W * N + (R_L + R_U) * 4.0 * W + N,
-            "ops_per_test": W if dom == "popcount" else 2 * KP,
+            "ops_per_test": ops_per_test[dom],
             "kernel_ms": count_ms,
         },
         "classify_forms": kern,
@@ -246,8 +257,10 @@ def scaling_leg(ctx, reps):
     KP = 64 * ((32 * W + 63) // 64)
     out = {"workload": "n=295, 1e5 upper Bernoulli(0.05) + 1e5 lower Bernoulli(0.9) rows, "
                        "N=1e6, COUNT mode", "tests": tests}
+    KP4 = 128 * ((32 * W + 127) // 128)
     for name, form, ops, peak in (("popcount", R.RSR_POPCOUNT, W, VALU_PEAK_OPS),
-                                  ("mfma", R.RSR_MFMA, 2 * KP, MFMA_I8_PEAK_OPS)):
+                                  ("mfma", R.RSR_MFMA, 2 * KP, MFMA_I8_PEAK_OPS),
+                                  ("mfma_fp4", R.RSR_MFMA_FP4, 2 * KP4, MFMA_FP4_PEAK_FLOPS)):
         ms = _event_ms(lambda: R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, form, flags=flags),
                        reps)
         ach = tests * ops / (ms * 1e-3)

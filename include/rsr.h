@@ -63,7 +63,7 @@ typedef enum {
 } rsr_status;
 
 enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
-enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2 };  /* rsr_classify form */
+enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2, RSR_MFMA_FP4 = 3 };  /* rsr_classify form */
 enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown which */
 enum { RSR_SYS_ST_CONNECTIVITY = 1 };                   /* rsr_system_desc kind */
 
@@ -181,9 +181,11 @@ rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint3
  *              rows (u32, device [N][2]).
  * form selects the kernel: RSR_POPCOUNT (bit-packed AND-NOT on the vector
  * ALU), RSR_MFMA (int8 matrix-core contraction of eq. violation_matrix, COUNT
- * and LABEL modes alike), RSR_AUTO (the faster one for this shape).  Every
- * form returns identical outputs.  EINVAL: refs built for another n/K,
- * N <= 0, NULL d_flags. */
+ * and LABEL modes alike), RSR_MFMA_FP4 (the same contraction with FP4 E2M1
+ * operands 0 / +-1 and fp32 accumulation, exact because every partial sum
+ * is a small integer), RSR_AUTO (the faster one for this shape).  Every form
+ * returns identical outputs.  EINVAL: refs built for another n/K, N <= 0,
+ * NULL d_flags.  EUNSUPPORTED: a matrix-core form with n*(K-1) > 1280. */
 rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_samples,
                         int64_t N, int32_t mode, int32_t form, uint8_t* d_flags,
                         uint32_t* d_match);

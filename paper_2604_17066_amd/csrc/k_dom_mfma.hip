@@ -10,6 +10,15 @@
 // is |t(r)| - |t(r) & t(x)| - 1 = |t(r) & ~t(x)| - 1, negative iff x >= r.
 // Pad rows (R rounded up to 16) and pad tiles are all zero and never match.
 //
+// Two operand formats share the kernel.  int8: one v_mfma_i32_16x16x64_i8
+// per 64 k, exact int32 accumulation.  FP4: 0 and +-1 are exact in FP4 E2M1
+// (nibbles 0x0, 0x2, 0xA), so v_mfma_scale_f32_16x16x128_f8f6f4 with unit
+// block scales contracts 128 k per instruction at twice the int8 rate, and the
+// fp32 accumulator holds the same integers exactly (|sum| <= 4096 < 2^24).
+// The FP4 starts are offset by 1/2 (-1/2 lower, |t(r)| - 1/2 upper, +1/2 pad)
+// so that no accumulator is ever a signed zero; a match is still exactly a
+// negative value, i.e. sign bit set, and the fold works on the raw bits.
+//
 // One v_mfma_i32_16x16x64_i8 multiplies a 16 x 64 tile of reference rows (A)
 // by a 64 x 16 tile of samples (B).  Lane l supplies row / column l % 16 and
 // the 16 bytes of k-chunk l / 16 of each operand; the result lane l holds rows
@@ -34,6 +43,23 @@ namespace rsr {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One k-step of the contraction: 64 k (int8) or 128 k (FP4) into acc.
+template <bool FP4>
+__device__ __forceinline__ v4i mfma_step(v4i a, v4i b, v4i acc) {
+    if constexpr (FP4) {
+        const v8i a8 = {a.x, a.y, a.z, a.w, 0, 0, 0, 0};
+        const v8i b8 = {b.x, b.y, b.z, b.w, 0, 0, 0, 0};
+        // Formats 4/4 = FP4 E2M1 for A and B; block scales 127 = 2^0 (E8M0).
+        const v4f r = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+            a8, b8, __builtin_bit_cast(v4f, acc), 4, 4, 0, 127, 0, 127);
+        return __builtin_bit_cast(v4i, r);
+    } else {
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
+    }
+}
 
 constexpr int kBlock = 512;
 constexpr int kWaves = kBlock / 64;
@@ -43,21 +69,33 @@ __device__ __forceinline__ int expand4(uint32_t v) {
     return static_cast<int>((v * 0x00204081u) & 0x01010101u);
 }
 
-// acc + 8 * (number of negative lanes of a).  v_perm_b32 selector bytes 9 and
-// 11 replicate bit 31 of the low and high source into a whole byte; 12 gives
-// a zero byte.
-__device__ __forceinline__ uint32_t add_negatives8(v4i a, uint32_t acc) {
-    const uint32_t p0 = __builtin_amdgcn_perm(static_cast<uint32_t>(a.x),
-                                              static_cast<uint32_t>(a.y), 0x0C0C0B09u);
-    const uint32_t p1 = __builtin_amdgcn_perm(static_cast<uint32_t>(a.z),
-                                              static_cast<uint32_t>(a.w), 0x0C0C0B09u);
-    return static_cast<uint32_t>(__builtin_popcount(p1)) +
-           (static_cast<uint32_t>(__builtin_popcount(p0)) + acc);
+__device__ __forceinline__ int expand8_fp4(uint32_t v) {
+    // Bits b0..b7 of v (v < 256) -> nibbles 2*b0 .. 2*b7 (FP4 E2M1 1.0 = 0x2).
+    v = (v | (v << 12)) & 0x000F000Fu;
+    v = (v | (v << 6)) & 0x03030303u;
+    v = (v | (v << 3)) & 0x11111111u;
+    return static_cast<int>(v << 1);
 }
 
+// acc + 8 * (number of negative values among the four of a).  The values are
+// first packed in pairs to int16 with saturation, which keeps their signs (for
+// the FP4 form the raw fp32 bits are used: a negative float is a negative
+// int32).  v_perm_b32 selector bytes 8..11 then replicate bits 15 / 31 of both
+// sources into four bytes, and one accumulating popcount adds them: four VALU
+// ops per v4i.  (Packing the FP4 form's floats with v_cvt_pkrtz_f16_f32
+// instead is not safe: the compiler treats the second operand of that pack as
+// unused in this pattern and drops it.)
+__device__ __forceinline__ uint32_t add_negatives8(v4i a, uint32_t acc) {
+    const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(a.x, a.y));
+    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(a.z, a.w));
+    return static_cast<uint32_t>(__builtin_popcount(__builtin_amdgcn_perm(lo, hi, 0x0B0A0908u))) + acc;
+}
+
+// Signed minimum of the four values (for FP4 the raw fp32 bits: a negative
+// float is a negative int32, which is all the test needs).
 __device__ __forceinline__ int min4(v4i a) { return min(min(a.x, a.y), min(a.z, a.w)); }
 
-template <int MT, bool COUNT>
+template <int MT, bool COUNT, bool FP4>
 __device__ __forceinline__ void fold(const v4i (&r)[MT], int (&acc_out)[MT]) {
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -84,8 +122,13 @@ constexpr int tiles_per_stage() {
 // workloads) four tiles measure faster than five: a block then covers 512
 // samples, and 10^6 samples make 7.6 rounds of blocks over 256 CUs instead of
 // 6.1, so the last, partly idle round costs less.
-template <int KS>
+template <int KS, bool FP4>
 constexpr int sample_tiles() {
+    // FP4: the instruction's 8-register operand slots raise the count a
+    // little; two tiles from KS = 9 on avoid spilling.  KS = 3 (up to 384 bits,
+    // the 295-edge workloads) takes four for the same reason as int8 KS = 5.
+    if (FP4 && KS == 3) return 4;
+    if (FP4 && KS >= 9) return 2;
     return KS <= 2 ? 8 : KS == 3 ? 7 : KS == 4 ? 6 : KS == 5 ? 4 : (KS >= 30 ? 1 : 30 / KS);
 }
 
@@ -95,7 +138,7 @@ constexpr int sample_tiles() {
 // accumulator starts, so the loop has no global load on its critical path;
 // tiles past the end are staged as zeros (never a match), so every group
 // runs all of its tiles without a branch.
-template <int KS, int MT, bool COUNT>
+template <int KS, int MT, bool COUNT, bool FP4>
 __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
                                           const v4i* __restrict__ cinit, int tiles,
                                           v4i* __restrict__ lds, int (&acc_out)[MT],
@@ -111,20 +154,29 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
     if (tiles <= 0) return;
     const int groups = (tiles + TPS - 1) / TPS;
 
+    // Each thread stages the same slots of every group: slot q is element
+    // `within` of tile t of the group, read from frag or cinit.  Its source
+    // pointer and per-group stride are fixed here; a group only adds a
+    // multiple of the stride.
     v4i stage[kPerThread];
+    const v4i* src[kPerThread];
+    int src_step[kPerThread], slot_tile[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int idx = q * kBlock + threadIdx.x;
+        const int t = idx / kTileV4, within = idx % kTileV4;
+        slot_tile[q] = idx < kStageV4 ? t : 1 << 30;  // out of the stage: never loaded
+        const bool is_frag = within < kFragV4;
+        src[q] = is_frag ? frag + static_cast<int64_t>(t) * kFragV4 + within
+                         : cinit + static_cast<int64_t>(t) * 4 + (within - kFragV4);
+        src_step[q] = is_frag ? TPS * kFragV4 : TPS * 4;
+    }
     auto fetch = [&](int G) {
 #pragma unroll
         for (int q = 0; q < kPerThread; ++q) {
-            const int idx = q * kBlock + threadIdx.x;
-            if (idx < kStageV4) {
-                const int t = idx / kTileV4, within = idx % kTileV4;
-                const int64_t T = static_cast<int64_t>(G) * TPS + t;
-                v4i v = {0, 0, 0, 0};
-                if (T < tiles)
-                    v = within < kFragV4 ? frag[T * kFragV4 + within]
-                                         : cinit[T * 4 + (within - kFragV4)];
-                stage[q] = v;
-            }
+            v4i v = {0, 0, 0, 0};
+            if (G * TPS + slot_tile[q] < tiles) v = src[q][static_cast<int64_t>(G) * src_step[q]];
+            stage[q] = v;
         }
     };
     auto store = [&](int buf) {
@@ -146,6 +198,10 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
         if (G + 1 < groups) fetch(G + 1);
 #pragma unroll
         for (int tt = 0; tt < TPS; ++tt) {
+            // Nothing crosses a tile start, so the fold of the previous tile
+            // (whose products are long finished) is scheduled among this
+            // tile's products instead of right behind its own.
+            __builtin_amdgcn_sched_barrier(0);
             const v4i* tile = lds + cur * kStageV4 + tt * kTileV4;
             const v4i c0 = tile[kFragV4 + grp];
             v4i a[KS];
@@ -156,9 +212,8 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
             for (int s = 0; s < KS; ++s)
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], bf[t][s],
-                                                                   s == 0 ? c0 : acc[t], 0, 0, 0);
-            fold<MT, COUNT>(prev, acc_out);
+                    acc[t] = mfma_step<FP4>(a[s], bf[t][s], s == 0 ? c0 : acc[t]);
+            fold<MT, COUNT, FP4>(prev, acc_out);
 #pragma unroll
             for (int t = 0; t < MT; ++t) prev[t] = acc[t];
             // The empty asm pins the fold to this tile: otherwise it sinks to
@@ -188,10 +243,10 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
         __syncthreads();
         if (leave) break;
     }
-    fold<MT, COUNT>(prev, acc_out);
+    fold<MT, COUNT, FP4>(prev, acc_out);
 }
 
-template <int KS, int MT, bool COUNT>
+template <int KS, int MT, bool COUNT, bool FP4>
 __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     const uint32_t* __restrict__ xs, int64_t N, int W, const v4i* __restrict__ low_frag,
     const v4i* __restrict__ low_c, int TL, const v4i* __restrict__ up_frag,
@@ -204,8 +259,11 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     const int col = lane & 15, grp = lane >> 4;
     const int64_t wbase = (static_cast<int64_t>(blockIdx.x) * kWaves + wave) * (16 * MT);
 
-    // Sample operand: bytes 16*grp .. +15 of k-step s are packed bits
+    // Sample operand.  int8: bytes 16*grp .. +15 of k-step s are packed bits
     // 64 s + 16 grp .. +15, i.e. half (grp & 1) of word 2 s + (grp >> 1).
+    // FP4: nibbles 32*grp .. +31 of k-step s are bits 128 s + 32 grp .. +31,
+    // i.e. the whole word 4 s + grp.  The reference fragments use the same
+    // positions, so A and B agree on the k of every operand element.
     v4i bf[MT][KS];
     bool valid[MT];
 #pragma unroll
@@ -214,14 +272,23 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
         valid[t] = h < N;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const int w = 2 * s + (grp >> 1);
-            uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * N + h] : 0u;
-            bits = (bits >> (16 * (grp & 1))) & 0xFFFFu;
             v4i f;
-            f.x = expand4(bits & 0xFu);
-            f.y = expand4((bits >> 4) & 0xFu);
-            f.z = expand4((bits >> 8) & 0xFu);
-            f.w = expand4(bits >> 12);
+            if constexpr (FP4) {
+                const int w = 4 * s + grp;
+                const uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * N + h] : 0u;
+                f.x = expand8_fp4(bits & 0xFFu);
+                f.y = expand8_fp4((bits >> 8) & 0xFFu);
+                f.z = expand8_fp4((bits >> 16) & 0xFFu);
+                f.w = expand8_fp4(bits >> 24);
+            } else {
+                const int w = 2 * s + (grp >> 1);
+                uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * N + h] : 0u;
+                bits = (bits >> (16 * (grp & 1))) & 0xFFFFu;
+                f.x = expand4(bits & 0xFu);
+                f.y = expand4((bits >> 4) & 0xFu);
+                f.z = expand4((bits >> 8) & 0xFu);
+                f.w = expand4(bits >> 12);
+            }
             bf[t][s] = f;
         }
     }
@@ -234,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
         accU[t] = 0;
         none[t] = false;
     }
-    mfma_pass<KS, MT, COUNT>(bf, low_frag, low_c, TL, lds, accL, none, valid, vote);
+    mfma_pass<KS, MT, COUNT, FP4>(bf, low_frag, low_c, TL, lds, accL, none, valid, vote);
 
     // Per-sample lower result across the four lane groups (COUNT: matches;
     // LABEL: negative iff some lower row matched).
@@ -268,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
         skip_upper = all != 0;
         __syncthreads();
     }
-    if (!skip_upper) mfma_pass<KS, MT, COUNT>(bf, up_frag, up_c, TU, lds, accU, lowered, valid, vote);
+    if (!skip_upper) mfma_pass<KS, MT, COUNT, FP4>(bf, up_frag, up_c, TU, lds, accU, lowered, valid, vote);
 
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -304,32 +371,44 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     }
 }
 
-template <int KS>
+template <int KS, bool FP4>
 hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
                      int mode, uint8_t* flags, uint32_t* match) {
-    constexpr int MT = sample_tiles<KS>();
+    constexpr int MT = sample_tiles<KS, FP4>();
     const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
     const dim3 grid(static_cast<unsigned>((N + per_block - 1) / per_block));
-    const v4i* lf = reinterpret_cast<const v4i*>(refs->d_lower_frag);
-    const v4i* lc = reinterpret_cast<const v4i*>(refs->d_lower_cinit);
-    const v4i* uf = reinterpret_cast<const v4i*>(refs->d_upper_frag);
-    const v4i* uc = reinterpret_cast<const v4i*>(refs->d_upper_cinit);
+    const v4i* lf = reinterpret_cast<const v4i*>(FP4 ? refs->d_lower_frag4 : refs->d_lower_frag);
+    const v4i* lc = FP4 ? reinterpret_cast<const v4i*>(refs->d_lower_cinit4)
+                        : reinterpret_cast<const v4i*>(refs->d_lower_cinit);
+    const v4i* uf = reinterpret_cast<const v4i*>(FP4 ? refs->d_upper_frag4 : refs->d_upper_frag);
+    const v4i* uc = FP4 ? reinterpret_cast<const v4i*>(refs->d_upper_cinit4)
+                        : reinterpret_cast<const v4i*>(refs->d_upper_cinit);
     if (mode == RSR_COUNT)
-        hipLaunchKernelGGL((k_dom_mfma<KS, MT, true>), grid, dim3(kBlock), 0, st, xs, N, refs->W,
-                           lf, lc, refs->TL, uf, uc, refs->TU, flags, match);
+        hipLaunchKernelGGL((k_dom_mfma<KS, MT, true, FP4>), grid, dim3(kBlock), 0, st, xs, N,
+                           refs->W, lf, lc, refs->TL, uf, uc, refs->TU, flags, match);
     else
-        hipLaunchKernelGGL((k_dom_mfma<KS, MT, false>), grid, dim3(kBlock), 0, st, xs, N, refs->W,
-                           lf, lc, refs->TL, uf, uc, refs->TU, flags, match);
+        hipLaunchKernelGGL((k_dom_mfma<KS, MT, false, FP4>), grid, dim3(kBlock), 0, st, xs, N,
+                           refs->W, lf, lc, refs->TL, uf, uc, refs->TU, flags, match);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
-                           int mode, uint8_t* flags, uint32_t* match) {
+                           int mode, bool fp4, uint8_t* flags, uint32_t* match) {
+    if (fp4) {
+        switch (refs->KS4) {
+#define RSR_KS_CASE(k) \
+    case k: return launch_ks<k, true>(st, refs, xs, N, mode, flags, match);
+            RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
+            RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
+#undef RSR_KS_CASE
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (refs->KS) {
 #define RSR_KS_CASE(k) \
-    case k: return launch_ks<k>(st, refs, xs, N, mode, flags, match);
+    case k: return launch_ks<k, false>(st, refs, xs, N, mode, flags, match);
         RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
         RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
         RSR_KS_CASE(11) RSR_KS_CASE(12) RSR_KS_CASE(13) RSR_KS_CASE(14) RSR_KS_CASE(15)

@@ -347,8 +347,11 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     const int KS = (W * 32 + 63) / 64;
     const bool with_mfma = KS <= rsr::kMaxMfmaSteps;
     const int TL = static_cast<int>((R_L + 15) / 16), TU = static_cast<int>((R_U + 15) / 16);
+    const int KS4 = (W * 32 + 127) / 128;
     std::vector<int8_t> lof, upf;
     std::vector<int32_t> loc, upc;
+    std::vector<uint8_t> lof4, upf4;
+    std::vector<float> loc4, upc4;
     if (with_mfma) {
         auto frag = [&](const uint32_t* words, int64_t r, int8_t value, std::vector<int8_t>& dst) {
             const int64_t T = r / 16;
@@ -373,6 +376,31 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
             int pop = 0;
             for (int w = 0; w < W; ++w) pop += __builtin_popcount(up[r * WR + w]);
             upc[r] = pop - 1;
+        }
+        // FP4 operands: 128 k per step; lane (group g, row rr) holds nibbles
+        // j = 0..31 for k = 128 s + 32 g + j, two per byte, low nibble first.
+        auto frag4 = [&](const uint32_t* words, int64_t r, uint8_t nib, std::vector<uint8_t>& dst) {
+            const int64_t T = r / 16;
+            const int rr = static_cast<int>(r % 16);
+            for (int k = 0; k < W * 32; ++k) {
+                if (!((words[k / 32] >> (k % 32)) & 1u)) continue;
+                const int s = k / 128, o = k % 128;
+                const int lane = (o / 32) * 16 + rr, j = o % 32;
+                dst[((static_cast<size_t>(T) * KS4 + s) * 64 + lane) * 16 + j / 2] |=
+                    static_cast<uint8_t>(nib << (4 * (j % 2)));
+            }
+        };
+        lof4.assign(static_cast<size_t>(TL) * KS4 * 1024, 0);
+        upf4.assign(static_cast<size_t>(TU) * KS4 * 1024, 0);
+        loc4.assign(static_cast<size_t>(TL) * 16, 0.5f);
+        upc4.assign(static_cast<size_t>(TU) * 16, 0.5f);
+        for (int64_t r = 0; r < R_L; ++r) {
+            frag4(lo.data() + r * WR, r, 0x2, lof4);  // +1.0
+            loc4[r] = -0.5f;
+        }
+        for (int64_t r = 0; r < R_U; ++r) {
+            frag4(up.data() + r * WR, r, 0xA, upf4);  // -1.0
+            upc4[r] = static_cast<float>(upc[r]) + 0.5f;  // |t(r)| - 0.5
         }
     }
 
@@ -401,6 +429,11 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
         upload(reinterpret_cast<void**>(&refs->d_lower_cinit), loc.data(), sizeof(int32_t) * loc.size());
         upload(reinterpret_cast<void**>(&refs->d_upper_frag), upf.data(), upf.size());
         upload(reinterpret_cast<void**>(&refs->d_upper_cinit), upc.data(), sizeof(int32_t) * upc.size());
+        refs->KS4 = KS4;
+        upload(reinterpret_cast<void**>(&refs->d_lower_frag4), lof4.data(), lof4.size());
+        upload(reinterpret_cast<void**>(&refs->d_lower_cinit4), loc4.data(), sizeof(float) * loc4.size());
+        upload(reinterpret_cast<void**>(&refs->d_upper_frag4), upf4.data(), upf4.size());
+        upload(reinterpret_cast<void**>(&refs->d_upper_cinit4), upc4.data(), sizeof(float) * upc4.size());
     }
     if (e != hipSuccess) {
         rsr_refs_destroy(refs);
@@ -430,6 +463,10 @@ rsr_status rsr_refs_destroy(rsr_refs* refs) {
     if (refs->d_lower_cinit) (void)hipFree(refs->d_lower_cinit);
     if (refs->d_upper_frag) (void)hipFree(refs->d_upper_frag);
     if (refs->d_upper_cinit) (void)hipFree(refs->d_upper_cinit);
+    if (refs->d_lower_frag4) (void)hipFree(refs->d_lower_frag4);
+    if (refs->d_lower_cinit4) (void)hipFree(refs->d_lower_cinit4);
+    if (refs->d_upper_frag4) (void)hipFree(refs->d_upper_frag4);
+    if (refs->d_upper_cinit4) (void)hipFree(refs->d_upper_cinit4);
     delete refs;
     return RSR_OK;
 }
@@ -503,14 +540,15 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
     if (!refs || !d_samples || !d_flags) return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
     if (mode != RSR_LABEL && mode != RSR_COUNT) return fail(ctx, RSR_EINVAL, "bad mode");
-    if (form != RSR_AUTO && form != RSR_POPCOUNT && form != RSR_MFMA)
+    if (form != RSR_AUTO && form != RSR_POPCOUNT && form != RSR_MFMA && form != RSR_MFMA_FP4)
         return fail(ctx, RSR_EINVAL, "bad form");
     if (refs->ctx->device != ctx->device) return fail(ctx, RSR_EINVAL, "refs on another device");
     DeviceGuard g(ctx->device);
-    if (form == RSR_MFMA && refs->KS == 0)
+    if ((form == RSR_MFMA && refs->KS == 0) || (form == RSR_MFMA_FP4 && refs->KS4 == 0))
         return fail(ctx, RSR_EUNSUPPORTED, "matrix-core form needs n*(K-1) <= 1280");
     uint32_t* match = mode == RSR_COUNT ? d_match : nullptr;
-    if (mode == RSR_LABEL && form != RSR_MFMA && refs->consistent && N <= 0x7FFFFFFFll) {
+    const bool matrix = form == RSR_MFMA || form == RSR_MFMA_FP4;
+    if (mode == RSR_LABEL && !matrix && refs->consistent && N <= 0x7FFFFFFFll) {
         rsr_status st = ensure_cascade(ctx, refs->W, N);
         if (st != RSR_OK) return st;
         rsr::CascadeBuffers cb;
@@ -528,8 +566,9 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
                                              rsr::CascadeShape{}, ctx->cu_count * 8));
         return RSR_OK;
     }
-    if (form == RSR_MFMA)
-        RSR_HIP(ctx, rsr::launch_dom_mfma(ctx->stream, refs, d_samples, N, mode, d_flags, match));
+    if (matrix)
+        RSR_HIP(ctx, rsr::launch_dom_mfma(ctx->stream, refs, d_samples, N, mode,
+                                          form == RSR_MFMA_FP4, d_flags, match));
     else
         RSR_HIP(ctx, rsr::launch_dom_bits(ctx->stream, refs, d_samples, N, mode, d_flags, match));
     return RSR_OK;

@@ -22,7 +22,8 @@ int dom_row_words(int W);
 constexpr int kMaxReduceBlocks = 1024;
 constexpr int kMaxGradBlocks = 64;
 // Largest k-step count of the matrix-core form (n (K-1) <= 1280 bits).
-constexpr int kMaxMfmaSteps = 20;
+constexpr int kMaxMfmaSteps = 20;   // int8 form: 64 k per step, 1280 bits
+constexpr int kMaxMfma4Steps = 10;  // FP4 form: 128 k per step, 1280 bits
 
 struct Workspace {
     uint64_t* counters = nullptr;      // 16 u64 device counters
@@ -68,6 +69,12 @@ struct rsr_refs {
     int32_t* d_lower_cinit = nullptr;    // [TL * 16]: -1 (row) or 0 (pad row)
     int8_t* d_upper_frag = nullptr;      // [TU][KS][64][16]: -t(r) as 0/-1 bytes
     int32_t* d_upper_cinit = nullptr;    // [TU * 16]: |t(r)| - 1 (row) or 0 (pad row)
+    // FP4 form: 128-wide k-steps, nibbles 0x2 (+1) / 0xA (-1), float starts.
+    int KS4 = 0;                          // ceil(32 W / 128)
+    int8_t* d_lower_frag4 = nullptr;      // [TL][KS4][64][16]: NOT t(r) as +1 nibbles
+    float* d_lower_cinit4 = nullptr;      // [TL * 16]: -0.5 (row) or +0.5 (pad row)
+    int8_t* d_upper_frag4 = nullptr;      // [TU][KS4][64][16]: t(r) as -1 nibbles
+    float* d_upper_cinit4 = nullptr;      // [TU * 16]: |t(r)| - 0.5 (row) or +0.5 (pad row)
 };
 
 struct rsr_system {
@@ -178,7 +185,7 @@ hipError_t launch_dom_bits(hipStream_t st, const rsr_refs* refs, const uint32_t*
 hipError_t launch_dom_cascade(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
                               const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap);
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
-                           int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match);
+                           int64_t N, int mode, bool fp4, uint8_t* d_flags, uint32_t* d_match);
 hipError_t launch_label(hipStream_t st, const SegSrc& seg, int32_t* d_list, uint64_t* d_counter,
                         int grid_cap);
 hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,

@@ -57,7 +57,7 @@ def test_sample_bit_identical(rsr_ctx, n, K, N, first, stream):
 
 # ------------------------------------------------------------- classifier ----
 
-FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA)
+FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4)
 
 
 def _classify_both(ctx, cfg, N, lower, upper, level=1):
@@ -321,6 +321,7 @@ def test_classify_forms_agree_and_deterministic(rsr_ctx):
     m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, cfg["N"])
     refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
     runs = [_np(R.rsr_classify(rsr_ctx, refs, xs, cfg["N"], R.RSR_COUNT, f, want_match=True)[1])
-            for f in (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA, R.RSR_POPCOUNT)]
+            for f in (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_MFMA,
+                      R.RSR_MFMA_FP4, R.RSR_POPCOUNT)]
     for r in runs[1:]:
         np.testing.assert_array_equal(r, runs[0])
