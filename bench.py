@@ -35,8 +35,8 @@ MFMA_FP4_PEAK_FLOPS = 10.1e15
 # changes, until the counters are taken again.
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
-    "mfma": None,
-    "mfma_fp4": None,
+    "mfma": (433.88 + 0.95) * 2 ** 20,
+    "mfma_fp4": (222.55 + 0.95) * 2 ** 20,
 }
 
 
