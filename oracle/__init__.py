@@ -61,6 +61,16 @@ def _load():
         "bf_reference_sets": (None, [ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int, _u8p, _i64p,
                                      _u8p, _i64p, ctypes.c_int64]),
         "or_state_prob": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _f64p, _u8p]),
+        "or_state_global": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, _u8p]),
+        "or_phi_global": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                         _u8p]),
+        "or_eval_global": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                            _u8p, _u8p, ctypes.c_int64, ctypes.c_int, _u8p]),
+        "or_boundary_global": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p,
+                                                ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int64,
+                                                _u8p, _u8p]),
+        "bf_state_table_global": (None, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                         _u8p]),
         "or_boundary_table": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int,
                                                _u8p, ctypes.c_int64, _u8p, _u8p]),
         "or_boundary_st": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p,
@@ -274,6 +284,52 @@ def reference_sets(table, n, K, level=1, cap=1 << 16):
     return lower[: nl.value].copy(), upper[: nu.value].copy()
 
 
+def state_global(graph, x):
+    """Global-connectivity system state of one state vector: 0 disconnected,
+    1 connected with a bridge, 2 two-edge-connected (edges work when x_e >= 1)."""
+    eu, ev = _graph_args(graph)
+    x = _c(x, np.uint8)
+    return int(_load().or_state_global(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                                       _ptr(ev, ctypes.c_int32), _ptr(x, ctypes.c_uint8)))
+
+
+def eval_unknown_global(graph, x, flags, which=0, level=1):
+    """As eval_unknown, for global connectivity at `level` (1 or 2)."""
+    eu, ev = _graph_args(graph)
+    x = _c(x, np.uint8)
+    N = x.shape[0]
+    flags = _c(flags, np.uint8) if flags is not None else np.zeros(N, dtype=np.uint8)
+    Y = np.zeros(N, dtype=np.uint8)
+    nev = _load().or_eval_global(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                                 _ptr(ev, ctypes.c_int32), int(level), _ptr(x, ctypes.c_uint8),
+                                 _ptr(flags, ctypes.c_uint8), N, int(which),
+                                 _ptr(Y, ctypes.c_uint8))
+    return Y, int(nev)
+
+
+def state_table_global(graph, K=2):
+    """Global-connectivity system state (0, 1, 2) of every one of the K^n states."""
+    eu, ev = _graph_args(graph)
+    n = eu.size
+    table = np.zeros(K ** n, dtype=np.uint8)
+    _load().bf_state_table_global(int(graph["n_nodes"]), n, _ptr(eu, ctypes.c_int32),
+                                  _ptr(ev, ctypes.c_int32), int(K), _ptr(table, ctypes.c_uint8))
+    return table
+
+
+def boundary_global(graph, x, K=2, level=1):
+    """Componentwise boundary search for global connectivity at `level`."""
+    eu, ev = _graph_args(graph)
+    x = _c(np.atleast_2d(x), np.uint8)
+    out = np.zeros_like(x)
+    side = np.zeros(x.shape[0], dtype=np.uint8)
+    nev = _load().or_boundary_global(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                                     _ptr(ev, ctypes.c_int32), int(level), int(K),
+                                     _ptr(x, ctypes.c_uint8), x.shape[0],
+                                     _ptr(out, ctypes.c_uint8), _ptr(side, ctypes.c_uint8))
+    return out, side, int(nev)
+
+
 def boundary_table(table, n, K, x, level=1):
     """Componentwise boundary search (section 3.4) with the system state given
     as a table over all K^n states.  Returns (states [Ns][n], side [Ns] with
@@ -303,7 +359,7 @@ def boundary_st(graph, x, K=2, level=1):
 
 
 def stage1(graph, p, N, picks, eps_u, max_rows, max_iters, seed, K=2, level=1, lower0=None,
-           upper0=None):
+           upper0=None, kind="st"):
     """The Stage-1 loop (section 3.5, fig. rsr_alg), written with the plain
     functions above.  Iteration it draws N samples (key seed, stream it),
     classifies them against the current rows (Algorithm 1), and stops when the
@@ -311,6 +367,7 @@ def stage1(graph, p, N, picks, eps_u, max_rows, max_iters, seed, K=2, level=1, l
     is the last iteration; otherwise it searches from the first `picks`
     unclassified samples in index order (section 3.4) and appends each result
     not already present, in pick order, up to max_rows rows in total.
+    kind = "global" uses global connectivity instead of s-t connectivity.
     Returns (lower rows, upper rows, dict of iterations, p_u, searches,
     duplicates)."""
     n = np.asarray(p).shape[0]
@@ -331,7 +388,8 @@ def stage1(graph, p, N, picks, eps_u, max_rows, max_iters, seed, K=2, level=1, l
         chosen = unknown[:picks]
         if chosen.size == 0:
             break
-        out, side, _ = boundary_st(graph, x[chosen], K=K, level=level)
+        search = boundary_global if kind == "global" else boundary_st
+        out, side, _ = search(graph, x[chosen], K=K, level=level)
         info["searches"] += chosen.size
         for r, sd in zip(out, side):
             if total >= max_rows:

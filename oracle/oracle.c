@@ -248,6 +248,79 @@ int or_phi_st(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, in
     return found;
 }
 
+/* ------------------------------------------------------------------------- */
+/* System function: global connectivity (section 4.3) and its levels (4.4)     */
+/* ------------------------------------------------------------------------- */
+/* Number of nodes reachable from node 0 over the edges with x_e >= 1, edge
+ * `skip` left out (skip = -1: none).  Plain queue BFS. */
+static int reach_count(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev,
+                       const uint8_t* x, int skip) {
+    uint8_t* seen = (uint8_t*)calloc((size_t)n_nodes, 1);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_nodes);
+    int head = 0, tail = 0;
+    seen[0] = 1;
+    queue[tail++] = 0;
+    while (head < tail) {
+        int u = queue[head++];
+        for (int e = 0; e < n_edges; ++e) {
+            if (e == skip || x[e] < 1) continue;
+            int w;
+            if (eu[e] == u) w = ev[e];
+            else if (ev[e] == u) w = eu[e];
+            else continue;
+            if (!seen[w]) {
+                seen[w] = 1;
+                queue[tail++] = w;
+            }
+        }
+    }
+    free(seen);
+    free(queue);
+    return tail;
+}
+
+/* System state of global connectivity over the working edges (x_e >= 1):
+ * 0 when some node is cut off from the rest, 1 when the graph is connected
+ * but some single edge failure would disconnect it, 2 when it stays
+ * connected after the failure of any one working edge (by Menger's theorem,
+ * two edge-disjoint paths between every pair of nodes).  Written as the
+ * definition: one BFS, then one BFS per working edge left out. */
+int or_state_global(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev,
+                    const uint8_t* x) {
+    if (reach_count(n_nodes, n_edges, eu, ev, x, -1) < n_nodes) return 0;
+    for (int e = 0; e < n_edges; ++e) {
+        if (x[e] < 1) continue;
+        if (reach_count(n_nodes, n_edges, eu, ev, x, e) < n_nodes) return 1;
+    }
+    return 2;
+}
+
+/* Phi for the target S >= level: 1 when or_state_global reaches level. */
+int or_phi_global(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int level,
+                  const uint8_t* x) {
+    return or_state_global(n_nodes, n_edges, eu, ev, x) >= level;
+}
+
+/* Stage 2 evaluation (section 3.5) for global connectivity: as or_eval. */
+int64_t or_eval_global(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int level,
+                       const uint8_t* x, const uint8_t* flags, int64_t N, int which,
+                       uint8_t* Y) {
+    int64_t evaluated = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : evaluated)
+    for (int64_t h = 0; h < N; ++h) {
+        const uint8_t* xh = x + (size_t)h * n_edges;
+        if (which == 0 && (flags[h] & 1)) {
+            Y[h] = 0;
+        } else if (which == 0 && (flags[h] & 2)) {
+            Y[h] = 1;
+        } else {
+            Y[h] = (uint8_t)or_phi_global(n_nodes, n_edges, eu, ev, level, xh);
+            evaluated += 1;
+        }
+    }
+    return evaluated;
+}
+
 /* Stage 2 evaluation of the system function (section 3.5): Y = 0 for a
  * lower-classified sample, 1 for an upper-classified one, Phi(x) for the
  * unclassified ones.  which = 1 evaluates Phi on every sample (plain Monte
@@ -368,6 +441,33 @@ int64_t or_boundary_st(int n_nodes, int n_edges, const int32_t* eu, const int32_
     return evals;
 }
 
+struct global_user {
+    int n_nodes, n_edges, level;
+    const int32_t *eu, *ev;
+};
+
+static int above_global(const uint8_t* x, const void* user) {
+    const struct global_user* u = (const struct global_user*)user;
+    return or_phi_global(u->n_nodes, u->n_edges, u->eu, u->ev, u->level, x);
+}
+
+/* Boundary search for global connectivity at `level` (components = edges). */
+int64_t or_boundary_global(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev,
+                           int level, int K, const uint8_t* x, int64_t Ns, uint8_t* out,
+                           uint8_t* side) {
+    struct global_user u = {n_nodes, n_edges, level, eu, ev};
+    int64_t evals = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : evals)
+    for (int64_t h = 0; h < Ns; ++h) {
+        int64_t e = 0;
+        memcpy(out + (size_t)h * n_edges, x + (size_t)h * n_edges, (size_t)n_edges);
+        side[h] = (uint8_t)boundary_search(n_edges, K, out + (size_t)h * n_edges, above_global,
+                                           &u, &e);
+        evals += e;
+    }
+    return evals;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Estimators (section 3.3.1)                                                 */
 /* ------------------------------------------------------------------------- */
@@ -462,6 +562,23 @@ void bf_phi_table_st(int n_nodes, int n_edges, const int32_t* eu, const int32_t*
         for (int64_t idx = 0; idx < (int64_t)total; ++idx) {
             index_to_state((uint64_t)idx, n_edges, K, x);
             table[idx] = (uint8_t)or_phi_st(n_nodes, n_edges, eu, ev, s, t, level, x);
+        }
+        free(x);
+    }
+}
+
+/* System state of global connectivity over every state (0, 1 or 2; compare
+ * with a level for Phi). */
+void bf_state_table_global(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int K,
+                           uint8_t* table) {
+    uint64_t total = state_count(n_edges, K);
+#pragma omp parallel
+    {
+        uint8_t* x = (uint8_t*)malloc((size_t)n_edges);
+#pragma omp for schedule(static)
+        for (int64_t idx = 0; idx < (int64_t)total; ++idx) {
+            index_to_state((uint64_t)idx, n_edges, K, x);
+            table[idx] = (uint8_t)or_state_global(n_nodes, n_edges, eu, ev, x);
         }
         free(x);
     }

@@ -3,7 +3,8 @@
 Each mutant is a copy of oracle/oracle.c with one plausible mistake planted
 (a swapped constant, an off-by-one, a flipped comparison, a dropped term, a
 wrong index).  It is compiled to a temporary library and the pin suites
-(test_oracle_pins.py, test_oracle_boundary.py) run against it in a subprocess; every mutant must make
+(test_oracle_pins.py, test_oracle_boundary.py, test_oracle_global.py) run
+against it in a subprocess; every mutant must make
 at least one pin fail.  This shows that the pins constrain every part of the
 oracle, not only that the oracle passes them."""
 import concurrent.futures as cf
@@ -33,8 +34,15 @@ MUTANTS = {
     "upper test: <= instead of <": ("if (x[i] < r[i]) return 0;", "if (x[i] <= r[i]) return 0;"),
     "no lower precedence": ("if (mode == 1 || cl == 0) {", "if (1) {"),
     "Phi ignores the level": ("if ((int)x[e] < level) continue;", "if ((int)x[e] < 1) continue;"),
-    "Phi: lower-flagged samples get Y = 1": ("if (which == 0 && (flags[h] & 1)) {\n            Y[h] = 0;",
-                                             "if (which == 0 && (flags[h] & 1)) {\n            Y[h] = 1;"),
+    "Phi (global): lower-flagged samples get Y = 1": ("if (which == 0 && (flags[h] & 1)) {\n            Y[h] = 0;",
+                                                      "if (which == 0 && (flags[h] & 1)) {\n            Y[h] = 1;"),
+    "Phi (s-t): lower-flagged samples get Y = 1": (
+        "schedule(dynamic, 256) reduction(+ : evaluated)\n    for (int64_t h = 0; h < N; ++h) {\n"
+        "        const uint8_t* xh = x + (size_t)h * n_edges;\n        if (which == 0 && (flags[h] & 1)) {\n"
+        "            Y[h] = 0;",
+        "schedule(dynamic, 256) reduction(+ : evaluated)\n    for (int64_t h = 0; h < N; ++h) {\n"
+        "        const uint8_t* xh = x + (size_t)h * n_edges;\n        if (which == 0 && (flags[h] & 1)) {\n"
+        "            Y[h] = 1;"),
     "estimate drops evaluated unknowns": ("double P = (double)(counts[1] + counts[4]) / Nd;",
                                           "double P = (double)(counts[1]) / Nd;"),
     "coefficient of variation inverted": ("sqrt((1.0 - P) / (Nd * P))", "sqrt(P / (Nd * (1.0 - P)))"),
@@ -53,8 +61,16 @@ MUTANTS = {
     "boundary: components visited in reverse": ("for (int i = 0; i < n; ++i) {\n        if (!start) {",
                                                 "for (int i = n - 1; i >= 0; --i) {\n        if (!start) {"),
     "boundary: sides swapped": ("        if (!start) {\n            while", "        if (start) {\n            while"),
+    "global: the left-out edge is still used": ("if (e == skip || x[e] < 1) continue;",
+                                                "if (x[e] < 1) continue;"),
+    "global: bridges ignored for level 2": ("if (reach_count(n_nodes, n_edges, eu, ev, x, e) < n_nodes) return 1;",
+                                            "if (reach_count(n_nodes, n_edges, eu, ev, x, e) < 0) return 1;"),
+    "global: strict level test": ("return or_state_global(n_nodes, n_edges, eu, ev, x) >= level;",
+                                  "return or_state_global(n_nodes, n_edges, eu, ev, x) > level;"),
+    "global: node 0 not counted": ("    seen[0] = 1;\n    queue[tail++] = 0;",
+                                   "    seen[0] = 1;\n    queue[tail++] = 0;\n    tail += 0 * head++;"),
 }
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_boundary.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_boundary.py", "test_oracle_global.py"]
 
 
 def _run(name, old, new, tmp):
