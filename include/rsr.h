@@ -65,7 +65,7 @@ typedef enum {
 enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
 enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2, RSR_MFMA_FP4 = 3 };  /* rsr_classify form */
 enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown which */
-enum { RSR_SYS_ST_CONNECTIVITY = 1 };                   /* rsr_system_desc kind */
+enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2 };  /* rsr_system_desc kind */
 
 /* Limits of this build. */
 #define RSR_MAX_K 16
@@ -92,17 +92,24 @@ typedef struct {
 
 /* System function description (section 2.1): components are the undirected
  * edges (edge_u[e], edge_v[e]) of a graph with n_nodes nodes; n_edges = n.
- * Phi = 1 when sink is reachable from source over edges whose state is at
- * least `level` (1 <= level <= K-1), else 0: single-OD connectivity for
- * K = 2, and the level-`level` bottleneck system for K > 2. */
+ *   RSR_SYS_ST_CONNECTIVITY: Phi = 1 when sink is reachable from source over
+ *     edges whose state is at least `level` (1 <= level <= K-1), else 0:
+ *     single-OD connectivity for K = 2, and the level-`level` bottleneck
+ *     system for K > 2 (section 4.1).
+ *   RSR_SYS_GLOBAL_CONNECTIVITY: edges work when their state is at least 1;
+ *     the system state is 0 when some node is cut off from the rest, 1 when
+ *     the working edges connect every node but some single edge failure
+ *     would disconnect them, 2 when every pair of nodes keeps two
+ *     edge-disjoint paths (no bridge); Phi = 1 when that state is at least
+ *     `level` (1 or 2) (sections 4.3 and 4.4).  source and sink are unused. */
 typedef struct {
-    int32_t kind;       /* RSR_SYS_ST_CONNECTIVITY */
+    int32_t kind;       /* RSR_SYS_ST_CONNECTIVITY or RSR_SYS_GLOBAL_CONNECTIVITY */
     int32_t n_nodes;    /* 2..RSR_MAX_NODES */
     int32_t n_edges;    /* = n, the number of components */
     int32_t K;          /* states per component */
     const int32_t* edge_u;  /* host [n_edges], node ids in [0, n_nodes) */
     const int32_t* edge_v;  /* host [n_edges] */
-    int32_t source, sink;   /* distinct node ids */
+    int32_t source, sink;   /* distinct node ids (s-t connectivity only) */
     int32_t level;
 } rsr_system_desc;
 
@@ -156,7 +163,8 @@ rsr_status rsr_refs_destroy(rsr_refs* refs);
 rsr_status rsr_refs_consistent(const rsr_refs* refs, int32_t* out);
 
 /* System function handle: copies the graph to the device.  EINVAL on a node
- * id out of range, source == sink, or level outside 1..K-1. */
+ * id out of range; for s-t connectivity on source == sink or level outside
+ * 1..K-1; for global connectivity on level outside 1..2. */
 rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* desc, rsr_system** out);
 rsr_status rsr_system_destroy(rsr_system* sys);
 

@@ -113,16 +113,20 @@ class Refs:
 
 
 class System:
-    """rsr_system: s-t connectivity of a graph at a level."""
+    """rsr_system: s-t connectivity of a graph at a level (kind "st"), or
+    global connectivity at level 1 (connected) or 2 (two-edge-connected)
+    (kind "global")."""
 
-    def __init__(self, ctx, graph, K=2, level=1):
+    def __init__(self, ctx, graph, K=2, level=1, kind="st"):
         eu = np.ascontiguousarray(graph["edge_u"], dtype=np.int32)
         ev = np.ascontiguousarray(graph["edge_v"], dtype=np.int32)
+        code = {"st": A.RSR_SYS_ST_CONNECTIVITY, "global": A.RSR_SYS_GLOBAL_CONNECTIVITY}[kind]
         desc = A.rsr_system_desc(
-            A.RSR_SYS_ST_CONNECTIVITY, int(graph["n_nodes"]), eu.size, int(K),
+            code, int(graph["n_nodes"]), eu.size, int(K),
             eu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-            int(graph["source"]), int(graph["sink"]), int(level))
+            int(graph.get("source", 0)), int(graph.get("sink", 0)), int(level))
+        self.kind = kind
         self.ctx, self.n, self.K, self.level = ctx, eu.size, int(K), int(level)
         h = ctypes.c_void_p()
         ctx.check(A.lib().rsr_system_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)))

@@ -29,23 +29,17 @@
 // wave read the marks before any lane writes in the same step, so a parent
 // always points at a node marked in an earlier step and the parent chain of
 // every marked node ends at s.
-#include "rsr_internal.h"
+#include "graph_search.h"
 
 namespace rsr {
 namespace {
 
+using graph::bit;
+using graph::fill;
+using graph::wave_sync;
+
 constexpr int kBoundaryBlock = 256;
 constexpr int kBoundaryWaves = kBoundaryBlock / 64;
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ uint32_t lds_bit(const uint32_t* set, uint32_t i) {
-    return (__hip_atomic_load(&set[i >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) >>
-            (i & 31)) & 1u;
-}
 
 // Per-wave LDS working set.
 struct WaveSets {
@@ -55,37 +49,12 @@ struct WaveSets {
     uint16_t* parent;  // [n_nodes] edge that marked the node
 };
 
-// Grows `set` over the lane's usable edges (bit k of `usable` = edge lane+64k)
-// until nothing changes or `sink` is marked; returns whether sink is marked.
-// With `parents`, records the marking edge of every newly marked node.
-__device__ bool grow(uint32_t* set, uint64_t usable, const uint32_t* __restrict__ s_edges,
-                     int sink, uint16_t* parent, bool parents) {
-    const int lane = threadIdx.x & 63;
-    while (true) {
-        bool changed = false;
-        uint64_t todo = usable;
-        while (todo) {
-            const int k = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-            todo &= todo - 1;
-            const int e = lane + 64 * k;
-            const uint32_t uv = s_edges[e];
-            const uint32_t u = uv & 0xFFFFu, v = uv >> 16;
-            const uint32_t ru = lds_bit(set, u), rv = lds_bit(set, v);
-            if (ru != rv) {
-                const uint32_t w = ru ? v : u;
-                if (parents) parent[w] = static_cast<uint16_t>(e);
-                atomicOr(&set[w >> 5], 1u << (w & 31));
-                changed = true;
-            }
-        }
-        wave_sync();
-        if (__builtin_amdgcn_readfirstlane(static_cast<int>(lds_bit(set, sink)))) return true;
-        if (!__any(changed)) return false;
-    }
-}
-
-__device__ __forceinline__ void fill(uint32_t* set, int words, uint32_t value) {
-    for (int w = threadIdx.x & 63; w < words; w += 64) set[w] = value;
+// s-t search from the nodes of `set` over the usable edges; parents recorded
+// when `parents`.
+__device__ __forceinline__ bool grow(uint32_t* set, uint64_t usable,
+                                     const uint32_t* __restrict__ s_edges, int sink,
+                                     uint16_t* parent, bool parents) {
+    return graph::grow(set, usable, s_edges, sink, parents ? parent : nullptr, nullptr);
 }
 
 // Marks the tree path from sink back to source in `path` (one lane walks it;
@@ -162,7 +131,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_boundary(
                 if ((mine_bits >> k) & 1u) continue;  // already usable: stays, walks to K-1
                 const uint32_t uv = s_edges[i];
                 const uint32_t u = uv & 0xFFFFu, v = uv >> 16;
-                const uint32_t ru = lds_bit(reach, u), rv = lds_bit(reach, v);
+                const uint32_t ru = bit(reach, u), rv = bit(reach, v);
                 bool take = true;
                 if (ru != rv) {
                     for (int w = lane; w < node_words; w += 64) trial[w] = reach[w];
@@ -187,7 +156,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_boundary(
                 const uint64_t mine_bits = __shfl(usable, owner);
                 if (!((mine_bits >> k) & 1u)) continue;  // unusable: walks to 0
                 bool take = true;
-                if (lds_bit(ws.path, static_cast<uint32_t>(i))) {
+                if (bit(ws.path, static_cast<uint32_t>(i))) {
                     const uint64_t without_i = usable & ~(lane == owner ? (1ull << k) : 0ull);
                     fill(ws.trial, node_words, 0u);
                     wave_sync();
@@ -214,13 +183,95 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_boundary(
     }
 }
 
+// Global connectivity (edges work at state >= 1; target S >= level, level 1
+// or 2): the same walk, with the system function evaluated from scratch at
+// every decisive step (a search from node 0, plus the bridge test for level
+// 2).  The one shortcut: for level 1 a survival state keeps the spanning tree
+// of its last search, and removing an edge outside that tree cannot
+// disconnect it.
+__global__ __launch_bounds__(kBoundaryBlock) void k_boundary_global(
+    const uint32_t* __restrict__ xs, int64_t N, const uint32_t* __restrict__ edges, int n_edges,
+    int n_nodes, int K, int level, const int64_t* __restrict__ pick, int64_t n_pick,
+    uint8_t* __restrict__ rows, uint8_t* __restrict__ side) {
+    extern __shared__ uint32_t lds[];
+    const int per_wave = graph::global_words(n_nodes, n_edges);
+    uint32_t* s_edges = lds;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const graph::GlobalSets g = graph::global_sets(lds + n_edges + wave * per_wave, n_nodes, n_edges);
+
+    for (int e = threadIdx.x; e < n_edges; e += kBoundaryBlock) s_edges[e] = edges[e];
+    __syncthreads();
+
+    const int rounds = (n_edges + 63) >> 6;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBoundaryWaves;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * kBoundaryWaves + wave; j < n_pick;
+         j += stride) {
+        const int64_t h = pick[j];
+        if (h < 0 || h >= N) {  // not a sample index: reported, nothing read
+            if (lane == 0) side[j] = 0xFF;
+            continue;
+        }
+        uint64_t usable = 0;  // plane 0 = [x >= 1]
+        for (int k = 0; k < rounds; ++k) {
+            const int e = lane + 64 * k;
+            if (e < n_edges) {
+                const uint32_t word = xs[static_cast<int64_t>(e >> 5) * N + h];
+                usable |= static_cast<uint64_t>((word >> (e & 31)) & 1u) << k;
+            }
+        }
+        // At level 1 the parents of a spanning tree of the usable edges are
+        // kept while the state survives.
+        const bool tree_mode = level == 1;
+        const bool survival =
+            graph::global_at_least(usable, level, s_edges, n_edges, n_nodes, g, tree_mode);
+        for (int i = 0; i < n_edges; ++i) {
+            const int owner = i & 63, k = i >> 6;
+            const bool ui = (__shfl(usable, owner) >> k) & 1u;
+            if (ui == !survival) continue;  // walks to K-1 (failure) or 0 (survival) unopposed
+            const uint64_t flip = lane == owner ? (1ull << k) : 0ull;
+            const uint64_t trial = survival ? (usable & ~flip) : (usable | flip);
+            bool take;
+            if (survival && tree_mode) {
+                const uint32_t uv = s_edges[i];
+                if (g.parent[uv & 0xFFFFu] != i && g.parent[uv >> 16] != i) {
+                    take = true;  // not a tree edge: the tree still spans every node
+                } else {
+                    take = graph::global_at_least(trial, 1, s_edges, n_edges, n_nodes, g, true);
+                    if (!take)  // restore the tree of the current edges
+                        graph::global_at_least(usable, 1, s_edges, n_edges, n_nodes, g, true);
+                }
+            } else {
+                const bool after = graph::global_at_least(trial, level, s_edges, n_edges, n_nodes, g);
+                take = survival ? after : !after;
+            }
+            if (take) usable = trial;
+        }
+        const uint8_t hi = static_cast<uint8_t>(survival ? 1 : K - 1);
+        uint8_t* out = rows + j * static_cast<int64_t>(n_edges);
+        for (int k = 0; k < rounds; ++k) {
+            const int e = lane + 64 * k;
+            if (e < n_edges) out[e] = ((usable >> k) & 1u) ? hi : 0;
+        }
+        if (lane == 0) side[j] = survival ? 1 : 0;
+        wave_sync();
+    }
+}
+
 }  // namespace
 
-size_t boundary_lds_bytes(int n_nodes, int n_edges) {
-    const int node_words = (n_nodes + 31) >> 5;
-    const int edge_words = (n_edges + 31) >> 5;
-    const int parent_words = (n_nodes + 1) >> 1;
-    const int per_wave = 2 * node_words + edge_words + parent_words;
+size_t boundary_lds_bytes(const rsr_system* sys) {
+    const int n_nodes = sys->n_nodes, n_edges = sys->n_edges;
+    size_t per_wave;
+    if (sys->kind == RSR_SYS_GLOBAL_CONNECTIVITY) {
+        per_wave = static_cast<size_t>(((n_nodes + 31) >> 5) + ((n_edges + 31) >> 5) +
+                                       2 * ((n_nodes + 1) >> 1));
+    } else {
+        const int node_words = (n_nodes + 31) >> 5;
+        const int edge_words = (n_edges + 31) >> 5;
+        const int parent_words = (n_nodes + 1) >> 1;
+        per_wave = static_cast<size_t>(2 * node_words + edge_words + parent_words);
+    }
     return sizeof(uint32_t) * (static_cast<size_t>(n_edges) + kBoundaryWaves * per_wave);
 }
 
@@ -230,11 +281,16 @@ hipError_t launch_boundary(hipStream_t st, const rsr_system* sys, const uint32_t
     int64_t blocks = (n_pick + kBoundaryWaves - 1) / kBoundaryWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
-    const size_t lds = boundary_lds_bytes(sys->n_nodes, sys->n_edges);
-    hipLaunchKernelGGL(k_boundary, dim3(static_cast<unsigned>(blocks)), dim3(kBoundaryBlock), lds,
-                       st, xs, N, plane_words(sys->n_edges), sys->d_edges, sys->n_edges,
-                       sys->n_nodes, sys->source, sys->sink, sys->K, sys->level, d_pick, n_pick,
-                       d_rows, d_side);
+    const size_t lds = boundary_lds_bytes(sys);
+    if (sys->kind == RSR_SYS_GLOBAL_CONNECTIVITY)
+        hipLaunchKernelGGL(k_boundary_global, dim3(static_cast<unsigned>(blocks)),
+                           dim3(kBoundaryBlock), lds, st, xs, N, sys->d_edges, sys->n_edges,
+                           sys->n_nodes, sys->K, sys->level, d_pick, n_pick, d_rows, d_side);
+    else
+        hipLaunchKernelGGL(k_boundary, dim3(static_cast<unsigned>(blocks)), dim3(kBoundaryBlock),
+                           lds, st, xs, N, plane_words(sys->n_edges), sys->d_edges, sys->n_edges,
+                           sys->n_nodes, sys->source, sys->sink, sys->K, sys->level, d_pick,
+                           n_pick, d_rows, d_side);
     return hipGetLastError();
 }
 

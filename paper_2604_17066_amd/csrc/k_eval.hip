@@ -14,7 +14,7 @@
 // new node or ends the search, so there are at most n_nodes sweeps.  The grid
 // is sized on the host without knowing the number of unclassified samples
 // (it lives on the device), and waves stride over the list.
-#include "rsr_internal.h"
+#include "graph_search.h"
 
 namespace rsr {
 namespace {
@@ -136,6 +136,50 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
     }
 }
 
+// Global connectivity (edges work at state >= 1, target S >= level, level 1
+// or 2) on the listed samples: one wavefront per sample, the same listing
+// and striding as k_bfs, the test of graph_search.h.
+__global__ __launch_bounds__(kBfsBlock) void k_global(
+    SegSrc seg, const uint32_t* __restrict__ edges, int n_edges, int n_nodes, int level,
+    const int32_t* __restrict__ list, const unsigned long long* __restrict__ count_ptr,
+    int which, unsigned long long* __restrict__ n_evaluated) {
+    extern __shared__ uint32_t lds[];
+    const int64_t N = seg.total;
+    const int64_t total = which == RSR_ALL ? N : static_cast<int64_t>(*count_ptr);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_evaluated)
+        *n_evaluated = static_cast<unsigned long long>(total);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * kWavesPerBfsBlock;
+    if (first >= total) return;  // uniform per block
+
+    uint32_t* s_edges = lds;
+    for (int e = threadIdx.x; e < n_edges; e += kBfsBlock) s_edges[e] = edges[e];
+    __syncthreads();
+    const graph::GlobalSets g = graph::global_sets(
+        lds + n_edges + wave * graph::global_words(n_nodes, n_edges), n_nodes, n_edges);
+    const int edge_rounds = (n_edges + 63) >> 6;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBfsBlock;
+    for (int64_t j = first + wave; j < total; j += stride) {
+        const int64_t g_idx = which == RSR_ALL ? j : static_cast<int64_t>(list[j]);
+        int job;
+        int64_t h, xstride;
+        seg_locate(seg, g_idx, job, h);
+        const uint32_t* xs = seg_words(seg, job, xstride);
+        uint64_t usable = 0;  // plane 0 = [x >= 1]
+        for (int k = 0; k < edge_rounds; ++k) {
+            const int e = lane + 64 * k;
+            if (e < n_edges) {
+                const uint32_t word = xs[static_cast<int64_t>(e >> 5) * xstride + h];
+                usable |= static_cast<uint64_t>((word >> (e & 31)) & 1u) << k;
+            }
+        }
+        const bool up = graph::global_at_least(usable, level, s_edges, n_edges, n_nodes, g);
+        if (lane == 0) seg_Y(seg, job)[h] = up ? 1 : 0;
+        graph::wave_sync();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_label(hipStream_t st, const SegSrc& seg, int32_t* d_list, uint64_t* d_counter,
@@ -154,6 +198,18 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
     const int64_t need = (seg.total + kWavesPerBfsBlock - 1) / kWavesPerBfsBlock;
     int blocks = static_cast<int>(need < grid_blocks ? need : grid_blocks);
     if (blocks < 1) blocks = 1;
+    if (sys->kind == RSR_SYS_GLOBAL_CONNECTIVITY) {
+        const size_t lds = sizeof(uint32_t) *
+            (static_cast<size_t>(sys->n_edges) +
+             kWavesPerBfsBlock * static_cast<size_t>(((sys->n_nodes + 31) >> 5) +
+                                                     ((sys->n_edges + 31) >> 5) +
+                                                     2 * ((sys->n_nodes + 1) >> 1)));
+        hipLaunchKernelGGL(k_global, dim3(blocks), dim3(kBfsBlock), lds, st, seg, sys->d_edges,
+                           sys->n_edges, sys->n_nodes, sys->level, d_list,
+                           reinterpret_cast<const unsigned long long*>(d_count), which,
+                           reinterpret_cast<unsigned long long*>(d_n_evaluated));
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_bfs, dim3(blocks), dim3(kBfsBlock), 0, st, seg, plane_words(sys->n_edges),
                        sys->level - 1, sys->d_edges, sys->n_edges, sys->n_nodes, sys->source,
                        sys->sink, d_list, reinterpret_cast<const unsigned long long*>(d_count),

@@ -474,17 +474,28 @@ rsr_status rsr_refs_destroy(rsr_refs* refs) {
 rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system** out) {
     if (!ctx || !out || !d) return RSR_EINVAL;
     *out = nullptr;
-    if (d->kind != RSR_SYS_ST_CONNECTIVITY)
-        return fail(ctx, RSR_EUNSUPPORTED, "only RSR_SYS_ST_CONNECTIVITY is supported");
+    if (d->kind != RSR_SYS_ST_CONNECTIVITY && d->kind != RSR_SYS_GLOBAL_CONNECTIVITY)
+        return fail(ctx, RSR_EINVAL, "unknown system kind");
+    const bool global = d->kind == RSR_SYS_GLOBAL_CONNECTIVITY;
     if (d->n_nodes < 2 || d->n_edges <= 0 || d->K < 2 || !d->edge_u || !d->edge_v)
         return fail(ctx, RSR_EINVAL, "bad graph size or NULL edge arrays");
     if (d->n_nodes > RSR_MAX_NODES || d->K > RSR_MAX_K ||
         static_cast<int64_t>(d->n_edges) * (d->K - 1) > RSR_MAX_BITS)
         return fail(ctx, RSR_EUNSUPPORTED, "graph exceeds RSR_MAX_NODES / RSR_MAX_BITS");
-    if (d->source < 0 || d->source >= d->n_nodes || d->sink < 0 || d->sink >= d->n_nodes ||
-        d->source == d->sink)
-        return fail(ctx, RSR_EINVAL, "source/sink out of range or equal");
-    if (d->level < 1 || d->level > d->K - 1) return fail(ctx, RSR_EINVAL, "level not in 1..K-1");
+    if (global) {
+        if (d->level < 1 || d->level > 2) return fail(ctx, RSR_EINVAL, "level not in 1..2");
+        // Edge list plus four waves' node sets, parents and depths in 64 KB of LDS.
+        const int64_t words = d->n_edges + 4ll * (((d->n_nodes + 31) >> 5) + ((d->n_edges + 31) >> 5) +
+                                                   2 * ((d->n_nodes + 1) >> 1));
+        if (words * 4 > 64 * 1024)
+            return fail(ctx, RSR_EUNSUPPORTED, "graph too large for the global-connectivity search");
+    } else {
+        if (d->source < 0 || d->source >= d->n_nodes || d->sink < 0 || d->sink >= d->n_nodes ||
+            d->source == d->sink)
+            return fail(ctx, RSR_EINVAL, "source/sink out of range or equal");
+        if (d->level < 1 || d->level > d->K - 1)
+            return fail(ctx, RSR_EINVAL, "level not in 1..K-1");
+    }
     std::vector<uint32_t> packed(d->n_edges);
     for (int e = 0; e < d->n_edges; ++e) {
         const int32_t u = d->edge_u[e], v = d->edge_v[e];
@@ -496,12 +507,13 @@ rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system*
     rsr_system* s = new (std::nothrow) rsr_system();
     if (!s) return fail(ctx, RSR_ENOMEM, "host allocation");
     s->ctx = ctx;
+    s->kind = d->kind;
     s->n_nodes = d->n_nodes;
     s->n_edges = d->n_edges;
     s->K = d->K;
     s->level = d->level;
-    s->source = d->source;
-    s->sink = d->sink;
+    s->source = global ? 0 : d->source;
+    s->sink = global ? 0 : d->sink;
     hipError_t e = hipMalloc(&s->d_edges, sizeof(uint32_t) * packed.size());
     if (e == hipSuccess)
         e = hipMemcpy(s->d_edges, packed.data(), sizeof(uint32_t) * packed.size(),
@@ -606,7 +618,7 @@ rsr_status rsr_boundary_search(rsr_ctx* ctx, const rsr_system* sys, const uint32
     if (!sys || !d_samples || !d_pick || !d_rows || !d_side)
         return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0 || N > 0x7FFFFFFFll) return fail(ctx, RSR_EINVAL, "N must be in 1..2^31-1");
-    if (rsr::boundary_lds_bytes(sys->n_nodes, sys->n_edges) > 64 * 1024)
+    if (rsr::boundary_lds_bytes(sys) > 64 * 1024)
         return fail(ctx, RSR_EUNSUPPORTED, "graph too large for the boundary search");
     DeviceGuard g(ctx->device);
     RSR_HIP(ctx, rsr::launch_boundary(ctx->stream, sys, d_samples, N, d_pick, n_pick, d_rows,

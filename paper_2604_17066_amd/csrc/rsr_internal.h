@@ -79,6 +79,7 @@ struct rsr_refs {
 
 struct rsr_system {
     rsr_ctx* ctx = nullptr;
+    int kind = RSR_SYS_ST_CONNECTIVITY;
     int n_nodes = 0, n_edges = 0, K = 0, level = 0, source = 0, sink = 0;
     uint32_t* d_edges = nullptr;  // [n_edges] packed (u | v << 16)
 };
@@ -192,7 +193,7 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
                       const int32_t* d_list, const uint64_t* d_count, int which,
                       uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
-size_t boundary_lds_bytes(int n_nodes, int n_edges);
+size_t boundary_lds_bytes(const rsr_system* sys);
 // First B unclassified samples in index order -> d_pick; *d_total = all of
 // them.  d_part: at least 1024 u64 of scratch.
 hipError_t launch_pick(hipStream_t st, const uint8_t* d_flags, int64_t N, int64_t B,

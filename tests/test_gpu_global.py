@@ -1,0 +1,109 @@
+"""GPU parity of global connectivity (sections 4.3-4.4): system-function
+evaluation at levels 1 (connected) and 2 (two-edge-connected), the boundary
+search, the whole Stage-2 path with brute-force reference sets, and the
+Stage-1 loop, all against the oracle on the same seeded samples."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_17066_amd as R
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    grid = WL.graphs.grid(3, 4)
+    rng = np.random.default_rng(61)
+    grid_p = WL.configs.binary_model(rng.uniform(0.8, 0.99, 17))
+    g1 = WL.configs.global1(N=10)
+    small = WL.rgg(30, 100, seed=62)           # two-edge-connected when intact
+    small_p = WL.configs.binary_model(np.random.default_rng(63).uniform(0.85, 0.99, 100))
+    # graph1 with lower survival so that both sides of level 1 are common
+    g1_p = WL.configs.binary_model(g1["p"][:, 1] * 0.88)
+    return {"grid": (grid, grid_p), "rgg30": (small, small_p), "graph1": (g1["graph"], g1_p)}
+
+
+@pytest.mark.parametrize("case", ["grid", "rgg30", "graph1"])
+@pytest.mark.parametrize("level", [1, 2])
+def test_global_eval_matches_oracle(rsr_ctx, case, level):
+    graph, p = _cases()[case]
+    N = 3000
+    m = R.Model(rsr_ctx, p)
+    xs = R.rsr_sample(rsr_ctx, m, 5, 0, 0, N)
+    system = R.System(rsr_ctx, graph, level=level, kind="global")
+    Y = R.rsr_eval_unknown(rsr_ctx, system, xs, N, None, which=R.RSR_ALL)
+    torch.cuda.synchronize()
+    x = oracle.sample(p, 5, 0, 0, N)
+    want, _ = oracle.eval_unknown_global(graph, x, None, which=1, level=level)
+    got = Y.cpu().numpy()
+    print(case, level, "P(S >= level) =", want.mean())
+    np.testing.assert_array_equal(got, want)
+    assert 0 < want.sum() < N or (case == "graph1" and level == 2)
+
+
+@pytest.mark.parametrize("case,level,n_pick", [("grid", 1, 600), ("grid", 2, 600),
+                                               ("rgg30", 1, 300), ("rgg30", 2, 40),
+                                               ("graph1", 1, 48)])
+def test_global_boundary_matches_oracle(rsr_ctx, case, level, n_pick):
+    graph, p = _cases()[case]
+    N = 2048
+    m = R.Model(rsr_ctx, p)
+    xs = R.rsr_sample(rsr_ctx, m, 8, 0, 0, N)
+    system = R.System(rsr_ctx, graph, level=level, kind="global")
+    picks = np.random.default_rng(64).choice(N, size=n_pick, replace=False).astype(np.int64)
+    rows, side = R.rsr_boundary_search(rsr_ctx, system, xs, N,
+                                       torch.tensor(picks, device=rsr_ctx.device))
+    torch.cuda.synchronize()
+    x = oracle.sample(p, 8, 0, 0, N)
+    want_rows, want_side, _ = oracle.boundary_global(graph, x[picks], level=level)
+    print(case, level, "survival picks:", int(want_side.sum()), "of", n_pick)
+    assert 0 < want_side.sum() < n_pick
+    np.testing.assert_array_equal(side.cpu().numpy(), want_side)
+    np.testing.assert_array_equal(rows.cpu().numpy(), want_rows)
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_global_stage2_path_matches_oracle(rsr_ctx, level):
+    """The grid's complete reference sets (brute force over 2^17 states), half
+    of each side given: labels, evaluations, estimate and gradient counts equal
+    the oracle's."""
+    graph, p = _cases()["grid"]
+    n, N = 17, 50_000
+    table = oracle.state_table_global(graph)
+    lo, up = oracle.reference_sets(table, n, 2, level=level)
+    lo, up = lo[::2], up[::2]
+    m = R.Model(rsr_ctx, p)
+    refs = R.Refs(rsr_ctx, n, 2, lo, up)
+    system = R.System(rsr_ctx, graph, level=level, kind="global")
+    est, buf = R.stage2(rsr_ctx, m, refs, system, N, 9)
+    _, counts = R.rsr_grad(rsr_ctx, m, buf.samples, buf.Y, N, want_counts=True)
+    torch.cuda.synchronize()
+    x = oracle.sample(p, 9, 0, 0, N)
+    flags, _, _ = oracle.classify(lo, up, x, mode=0)
+    Y, _ = oracle.eval_unknown_global(graph, x, flags, level=level)
+    cnt = oracle.counts(flags, Y)
+    want = oracle.estimate(cnt)
+    np.testing.assert_array_equal(buf.flags.cpu().numpy(), flags)
+    np.testing.assert_array_equal(buf.Y.cpu().numpy(), Y)
+    assert est["P"] == want[3] and est["n_u"] == int(cnt[2])
+    assert 0 < est["n_u"] < N
+    wcounts, _ = oracle.grad(p, x, Y)
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), wcounts)
+
+
+@pytest.mark.parametrize("case,level", [("grid", 1), ("grid", 2), ("graph1", 1)])
+def test_global_stage1_loop_matches_oracle(rsr_ctx, case, level):
+    graph, p = _cases()[case]
+    N, picks, iters = (3000, 16, 10) if case == "grid" else (4000, 32, 3)
+    m = R.Model(rsr_ctx, p)
+    system = R.System(rsr_ctx, graph, level=level, kind="global")
+    lo, up, info = R.stage1(rsr_ctx, m, system, N, picks, 1e-9, 10_000, iters, 23)
+    wlo, wup, winfo = oracle.stage1(graph, p, N, picks, 1e-9, 10_000, iters, 23, level=level,
+                                    kind="global")
+    print(case, level, info)
+    for key in ("iterations", "p_u", "searches", "duplicates"):
+        assert info[key] == winfo[key], key
+    np.testing.assert_array_equal(lo, wlo)
+    np.testing.assert_array_equal(up, wup)

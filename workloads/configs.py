@@ -50,6 +50,33 @@ def tiny(N=100_000):
 
 
 @functools.lru_cache(maxsize=None)
+def _graph1():
+    g = G.rgg(59, 262, seed=1)
+    s, t = G.st_degree_rule(g)
+    return G.with_terminals(g, s, t)
+
+
+def global1(N=1_000_000):
+    """Global connectivity of a 59-node / 262-edge random geometric graph (the
+    size of the paper's Graph 1) with edge failure p ~ U[0.01, 0.20]; the
+    reference states are grown by the Stage-1 loop, so none are given."""
+    g = _graph1()
+    n = g["edge_u"].size
+    rng = np.random.default_rng(21)
+    return {"name": "global1", "graph": g, "n": n, "K": 2,
+            "p": binary_model(1.0 - rng.uniform(0.01, 0.20, n)), "seed": 21, "stream": 0,
+            "N": int(N)}
+
+
+def global2(N=1_000_000):
+    """Global connectivity of graph2 (119 nodes / 295 edges) with its edge
+    probabilities; reference states grown by the Stage-1 loop."""
+    c = graph2(N=N, R_U=10, R_L=10)
+    return {"name": "global2", "graph": c["graph"], "n": c["n"], "K": 2, "p": c["p"],
+            "seed": 22, "stream": 0, "N": int(N)}
+
+
+@functools.lru_cache(maxsize=None)
 def _graph2():
     g = G.rgg(119, 295, seed=2)
     s, t = G.st_degree_rule(g)

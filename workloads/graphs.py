@@ -97,3 +97,19 @@ def with_terminals(graph, s, t):
 def edge_midpoints(graph):
     pos = graph["pos"]
     return 0.5 * (pos[graph["edge_u"]] + pos[graph["edge_v"]])
+
+
+def grid(rows: int, cols: int):
+    """rows x cols grid graph (node r*cols + c), edges row-major then
+    column-major; two-edge-connected for rows, cols >= 2."""
+    eu, ev = [], []
+    for r in range(rows):
+        for c in range(cols - 1):
+            eu.append(r * cols + c)
+            ev.append(r * cols + c + 1)
+    for r in range(rows - 1):
+        for c in range(cols):
+            eu.append(r * cols + c)
+            ev.append((r + 1) * cols + c)
+    return {"n_nodes": rows * cols, "edge_u": np.array(eu, dtype=np.int32),
+            "edge_v": np.array(ev, dtype=np.int32), "source": 0, "sink": rows * cols - 1}
