@@ -180,6 +180,7 @@ def main():
         extra["multi_state"] = multi_leg(ctx, reps)
         extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps)
         extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
+        extra["global_connectivity"] = global_leg(ctx)
 
     out = {
         "metric": "dominance tests/s (samples x reference states), whole Stage-2 step",
@@ -349,6 +350,56 @@ def stage1_leg(ctx, with_cpu):
         out["cpu_baseline"] = cpu_baseline_boundary(cfg, 9, 256)
     log(f"stage 1: {info['iterations']} iterations, {out['rows']} rows, p_u {info['p_u']:.2e}, "
         f"{loop_s:.2f} s; boundary search {out['boundary_searches_per_s']:.3g}/s")
+    return out
+
+
+def global_leg(ctx):
+    """Global connectivity (sections 4.3-4.4) on graph2 (119 nodes / 295
+    edges): Stage 1 from empty reference sets (1e5 samples and 8192 searches
+    per iteration, until 1e5 rows or p_u < 1e-5), then Stage 2 with those rows
+    on 1e6 samples, for the connected level; and the boundary-search rate of
+    both levels."""
+    import time as _t
+    import torch
+    import paper_2604_17066_amd as R
+    import workloads as WL
+    cfg = WL.configs.global2(N=1)
+    model = R.Model(ctx, cfg["p"])
+    out = {"workload": "global connectivity of graph2 (119 nodes / 295 edges), p_fail ~ U[0.01, 0.20]"}
+    for level in (1, 2):
+        system = R.System(ctx, cfg["graph"], level=level, kind="global")
+        N = 1 << 16
+        xs = R.rsr_sample(ctx, model, 9, 0, 0, N)
+        picks = torch.arange(0, N, dtype=torch.int64, device=ctx.device)
+        rows, side = R.rsr_boundary_search(ctx, system, xs, N, picks)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        R.rsr_boundary_search(ctx, system, xs, N, picks, rows=rows, side=side)
+        torch.cuda.synchronize()
+        out[f"level{level}_boundary_searches_per_s"] = N / (_t.perf_counter() - t0)
+    system = R.System(ctx, cfg["graph"], level=1, kind="global")
+    R.stage1(ctx, model, system, 10_000, 64, 1e-5, 200, 3, 1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    lo, up, info = R.stage1(ctx, model, system, 100_000, 8192, 1e-5, 100_000, 200, 7)
+    stage1_s = _t.perf_counter() - t0
+    refs = R.Refs(ctx, cfg["n"], 2, lo, up)
+    N2 = 1_000_000
+    est, buf = R.stage2(ctx, model, refs, system, N2, 99)
+    torch.cuda.synchronize()
+    t1 = _t.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        est, buf = R.stage2(ctx, model, refs, system, N2, 99, buffers=buf)
+    torch.cuda.synchronize()
+    stage2_ms = (_t.perf_counter() - t1) * 1e3 / reps
+    out.update({"stage1_s": stage1_s, "stage1": info, "rows": len(lo) + len(up),
+                "stage2_ms_N1e6": stage2_ms, "P_connected": est["P"], "p_u": est["p_u"],
+                "se": est["se"]})
+    log(f"global connectivity: stage 1 {info['iterations']} iterations, {len(lo) + len(up)} rows, "
+        f"{stage1_s:.2f} s; stage 2 (N=1e6) {stage2_ms:.2f} ms, P={est['P']:.5f}, "
+        f"p_u={est['p_u']:.3e}; boundary search {out['level1_boundary_searches_per_s']:.3g}/s "
+        f"(level 1), {out['level2_boundary_searches_per_s']:.3g}/s (level 2)")
     return out
 
 

@@ -280,8 +280,12 @@ rsr_status rsr_model_destroy(rsr_model* m) {
     return RSR_OK;
 }
 
-rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower, int64_t R_L,
-                           const uint8_t* upper, int64_t R_U, rsr_refs** out) {
+}  // extern "C"
+
+namespace rsr {
+
+rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower, int64_t R_L,
+                       const uint8_t* upper, int64_t R_U, bool matrix_operands, rsr_refs** out) {
     if (!ctx || !out) return RSR_EINVAL;
     *out = nullptr;
     if (n <= 0 || K < 2) return fail(ctx, RSR_EINVAL, "n must be > 0 and K >= 2");
@@ -345,7 +349,7 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     // |t(r)| - 1, so the result is |t(r) & ~t(x)| - 1.  Pad rows and pad
     // tiles are all zero: result 0, never a match.
     const int KS = (W * 32 + 63) / 64;
-    const bool with_mfma = KS <= rsr::kMaxMfmaSteps;
+    const bool with_mfma = matrix_operands && KS <= rsr::kMaxMfmaSteps;
     const int TL = static_cast<int>((R_L + 15) / 16), TU = static_cast<int>((R_U + 15) / 16);
     const int KS4 = (W * 32 + 127) / 128;
     std::vector<int8_t> lof, upf;
@@ -448,10 +452,19 @@ rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lo
     return RSR_OK;
 }
 
+}  // namespace rsr
+
+extern "C" {
+
 rsr_status rsr_refs_consistent(const rsr_refs* refs, int32_t* out) {
     if (!refs || !out) return RSR_EINVAL;
     *out = refs->consistent ? 1 : 0;
     return RSR_OK;
+}
+
+rsr_status rsr_refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower, int64_t R_L,
+                           const uint8_t* upper, int64_t R_U, rsr_refs** out) {
+    return rsr::refs_create(ctx, n, K, lower, R_L, upper, R_U, true, out);
 }
 
 rsr_status rsr_refs_destroy(rsr_refs* refs) {

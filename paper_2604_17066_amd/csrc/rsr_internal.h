@@ -194,6 +194,10 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
                       uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
 size_t boundary_lds_bytes(const rsr_system* sys);
+// rsr_refs_create; without matrix_operands the MFMA fragments are not built
+// (the handle then serves the popcount and cascade forms only).
+rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower, int64_t R_L,
+                       const uint8_t* upper, int64_t R_U, bool matrix_operands, rsr_refs** out);
 // First B unclassified samples in index order -> d_pick; *d_total = all of
 // them.  d_part: at least 1024 u64 of scratch.
 hipError_t launch_pick(hipStream_t st, const uint8_t* d_flags, int64_t N, int64_t B,

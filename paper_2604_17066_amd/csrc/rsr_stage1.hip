@@ -108,7 +108,10 @@ extern "C" rsr_status rsr_stage1(rsr_ctx* ctx, const rsr_model* model, const rsr
         const int64_t R_L = static_cast<int64_t>(rows_l.size() / row);
         const int64_t R_U = static_cast<int64_t>(rows_u.size() / row);
         RefsHandle refs;
-        rsr_status st = rsr_refs_create(ctx, n, K, rows_l.data(), R_L, rows_u.data(), R_U, &refs.r);
+        // The loop classifies with the popcount / cascade forms only, so the
+        // matrix-core operands are not built.
+        rsr_status st = rsr::refs_create(ctx, n, K, rows_l.data(), R_L, rows_u.data(), R_U, false,
+                                         &refs.r);
         if (st != RSR_OK) return st;
         st = rsr_sample(ctx, model, P.seed, static_cast<uint32_t>(it), 0, N,
                         static_cast<uint32_t*>(samples.p));
