@@ -242,9 +242,10 @@ def _event_ms(fn, reps):
 
 
 def scaling_leg(ctx, reps):
-    """Kernel-only workload (n = 295, 1e5 + 1e5 Bernoulli rows, N = 1e6), both
-    classification forms in COUNT mode (every test in full) against their
-    rooflines."""
+    """Kernel-only workload (n = 295, 1e5 + 1e5 Bernoulli rows, N = 1e6), every
+    classification form in COUNT mode (every test in full) against its
+    roofline, and in LABEL mode (these rows are not a consistent reference
+    set, so the cascade does not apply)."""
     import paper_2604_17066_amd as R
     import workloads as WL
     cfg = WL.configs.scaling()
@@ -265,9 +266,13 @@ def scaling_leg(ctx, reps):
         ms = _event_ms(lambda: R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, form, flags=flags),
                        reps)
         ach = tests * ops / (ms * 1e-3)
+        label_ms = _event_ms(lambda: R.rsr_classify(ctx, refs, xs, N, R.RSR_LABEL, form,
+                                                    flags=flags), reps)
         out[name] = {"kernel_ms": ms, "tests_per_s": tests / (ms * 1e-3), "achieved_TOPs": ach / 1e12,
-                     "peak_TOPs": peak / 1e12, "frac": ach / peak, "ops_per_test": ops}
-        log(f"scaling COUNT {name}: {ms:.2f} ms, {ach / peak * 100:.1f}% of peak")
+                     "peak_TOPs": peak / 1e12, "frac": ach / peak, "ops_per_test": ops,
+                     "label_ms": label_ms}
+        log(f"scaling COUNT {name}: {ms:.2f} ms, {ach / peak * 100:.1f}% of peak; "
+            f"LABEL {label_ms:.2f} ms")
     return out
 
 

@@ -191,7 +191,8 @@ rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint3
  * ALU), RSR_MFMA (int8 matrix-core contraction of eq. violation_matrix, COUNT
  * and LABEL modes alike), RSR_MFMA_FP4 (the same contraction with FP4 E2M1
  * operands 0 / +-1 and fp32 accumulation, exact because every partial sum
- * is a small integer), RSR_AUTO (the faster one for this shape).  Every form
+ * is a small integer), RSR_AUTO (the cascade for LABEL mode on consistent
+ * rows, else the FP4 form up to 1280 bits, else the popcount form).  Every form
  * returns identical outputs.  EINVAL: refs built for another n/K, N <= 0,
  * NULL d_flags.  EUNSUPPORTED: a matrix-core form with n*(K-1) > 1280. */
 rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_samples,

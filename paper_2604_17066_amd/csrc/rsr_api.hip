@@ -572,6 +572,11 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
     if ((form == RSR_MFMA && refs->KS == 0) || (form == RSR_MFMA_FP4 && refs->KS4 == 0))
         return fail(ctx, RSR_EUNSUPPORTED, "matrix-core form needs n*(K-1) <= 1280");
     uint32_t* match = mode == RSR_COUNT ? d_match : nullptr;
+    // RSR_AUTO: the cascade for LABEL on consistent rows (each sample stops at
+    // its first match); otherwise the FP4 matrix-core form, which makes the
+    // most tests per second in both modes; popcount beyond 1280 bits.
+    if (form == RSR_AUTO && refs->KS4 > 0 && (mode == RSR_COUNT || !refs->consistent))
+        form = RSR_MFMA_FP4;
     const bool matrix = form == RSR_MFMA || form == RSR_MFMA_FP4;
     if (mode == RSR_LABEL && !matrix && refs->consistent && N <= 0x7FFFFFFFll) {
         rsr_status st = ensure_cascade(ctx, refs->W, N);
