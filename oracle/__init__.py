@@ -71,6 +71,16 @@ def _load():
                                                 _u8p, _u8p]),
         "bf_state_table_global": (None, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
                                          _u8p]),
+        "or_maxflow_st": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                         ctypes.c_int, _u8p]),
+        "or_eval_flow": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, _u8p, _u8p, ctypes.c_int64,
+                                          ctypes.c_int, _u8p]),
+        "or_boundary_flow": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, _u8p, ctypes.c_int64, _u8p, _u8p]),
+        "bf_maxflow_table": (None, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, _u8p]),
         "or_boundary_table": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _u8p, ctypes.c_int,
                                                _u8p, ctypes.c_int64, _u8p, _u8p]),
         "or_boundary_st": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int, _i32p, _i32p,
@@ -330,6 +340,54 @@ def boundary_global(graph, x, K=2, level=1):
     return out, side, int(nev)
 
 
+def maxflow_st(graph, x):
+    """Maximum s-t flow with edge capacities x (Edmonds-Karp)."""
+    eu, ev = _graph_args(graph)
+    x = _c(x, np.uint8)
+    return int(_load().or_maxflow_st(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                                     _ptr(ev, ctypes.c_int32), int(graph["source"]),
+                                     int(graph["sink"]), _ptr(x, ctypes.c_uint8)))
+
+
+def eval_unknown_flow(graph, x, flags, which=0, demand=1):
+    """As eval_unknown, for the target max flow >= demand."""
+    eu, ev = _graph_args(graph)
+    x = _c(x, np.uint8)
+    N = x.shape[0]
+    flags = _c(flags, np.uint8) if flags is not None else np.zeros(N, dtype=np.uint8)
+    Y = np.zeros(N, dtype=np.uint8)
+    nev = _load().or_eval_flow(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                               _ptr(ev, ctypes.c_int32), int(graph["source"]), int(graph["sink"]),
+                               int(demand), _ptr(x, ctypes.c_uint8), _ptr(flags, ctypes.c_uint8),
+                               N, int(which), _ptr(Y, ctypes.c_uint8))
+    return Y, int(nev)
+
+
+def maxflow_table(graph, K):
+    """Max flow (capped at 255) of every one of the K^n states."""
+    eu, ev = _graph_args(graph)
+    n = eu.size
+    table = np.zeros(K ** n, dtype=np.uint8)
+    _load().bf_maxflow_table(int(graph["n_nodes"]), n, _ptr(eu, ctypes.c_int32),
+                             _ptr(ev, ctypes.c_int32), int(graph["source"]), int(graph["sink"]),
+                             int(K), _ptr(table, ctypes.c_uint8))
+    return table
+
+
+def boundary_flow(graph, x, K, demand):
+    """Componentwise boundary search for the target max flow >= demand."""
+    eu, ev = _graph_args(graph)
+    x = _c(np.atleast_2d(x), np.uint8)
+    out = np.zeros_like(x)
+    side = np.zeros(x.shape[0], dtype=np.uint8)
+    nev = _load().or_boundary_flow(int(graph["n_nodes"]), eu.size, _ptr(eu, ctypes.c_int32),
+                                   _ptr(ev, ctypes.c_int32), int(graph["source"]),
+                                   int(graph["sink"]), int(demand), int(K),
+                                   _ptr(x, ctypes.c_uint8), x.shape[0],
+                                   _ptr(out, ctypes.c_uint8), _ptr(side, ctypes.c_uint8))
+    return out, side, int(nev)
+
+
 def boundary_table(table, n, K, x, level=1):
     """Componentwise boundary search (section 3.4) with the system state given
     as a table over all K^n states.  Returns (states [Ns][n], side [Ns] with
@@ -367,7 +425,8 @@ def stage1(graph, p, N, picks, eps_u, max_rows, max_iters, seed, K=2, level=1, l
     is the last iteration; otherwise it searches from the first `picks`
     unclassified samples in index order (section 3.4) and appends each result
     not already present, in pick order, up to max_rows rows in total.
-    kind = "global" uses global connectivity instead of s-t connectivity.
+    kind = "global" uses global connectivity instead of s-t connectivity, and
+    kind = "flow" the target max flow >= level.
     Returns (lower rows, upper rows, dict of iterations, p_u, searches,
     duplicates)."""
     n = np.asarray(p).shape[0]
@@ -388,8 +447,11 @@ def stage1(graph, p, N, picks, eps_u, max_rows, max_iters, seed, K=2, level=1, l
         chosen = unknown[:picks]
         if chosen.size == 0:
             break
-        search = boundary_global if kind == "global" else boundary_st
-        out, side, _ = search(graph, x[chosen], K=K, level=level)
+        if kind == "flow":
+            out, side, _ = boundary_flow(graph, x[chosen], K, level)
+        else:
+            search = boundary_global if kind == "global" else boundary_st
+            out, side, _ = search(graph, x[chosen], K=K, level=level)
         info["searches"] += chosen.size
         for r, sd in zip(out, side):
             if total >= max_rows:

@@ -321,6 +321,63 @@ int64_t or_eval_global(int n_nodes, int n_edges, const int32_t* eu, const int32_
     return evaluated;
 }
 
+/* ------------------------------------------------------------------------- */
+/* System function: single-OD maximum flow (section 2.2, d-MPs and d-MCs)      */
+/* ------------------------------------------------------------------------- */
+/* Maximum s-t flow when undirected edge e carries up to x[e] units in either
+ * direction (the component state is the capacity).  Edmonds-Karp: repeat a
+ * breadth-first search for a shortest path with spare capacity and push its
+ * bottleneck along it, until no such path is left.  flow[e] > 0 is flow from
+ * eu[e] to ev[e]. */
+int or_maxflow_st(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int s, int t,
+                  const uint8_t* x) {
+    if (s == t) return 1 << 30;
+    int* flow = (int*)calloc((size_t)n_edges, sizeof(int));
+    int* via = (int*)malloc(sizeof(int) * (size_t)n_nodes);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_nodes);
+    int total = 0;
+    for (;;) {
+        for (int v = 0; v < n_nodes; ++v) via[v] = -1;
+        via[s] = n_edges;  /* marks s as reached */
+        int head = 0, tail = 0;
+        queue[tail++] = s;
+        while (head < tail && via[t] < 0) {
+            int u = queue[head++];
+            for (int e = 0; e < n_edges; ++e) {
+                int w, spare;
+                if (eu[e] == u) { w = ev[e]; spare = x[e] - flow[e]; }
+                else if (ev[e] == u) { w = eu[e]; spare = x[e] + flow[e]; }
+                else continue;
+                if (spare > 0 && via[w] < 0) {
+                    via[w] = e;
+                    queue[tail++] = w;
+                }
+            }
+        }
+        if (via[t] < 0) break;
+        /* bottleneck along the path, then push it */
+        int push = 1 << 30;
+        for (int w = t; w != s;) {
+            int e = via[w];
+            int from = (ev[e] == w) ? eu[e] : ev[e];
+            int spare = (from == eu[e]) ? x[e] - flow[e] : x[e] + flow[e];
+            if (spare < push) push = spare;
+            w = from;
+        }
+        for (int w = t; w != s;) {
+            int e = via[w];
+            int from = (ev[e] == w) ? eu[e] : ev[e];
+            if (from == eu[e]) flow[e] += push; else flow[e] -= push;
+            w = from;
+        }
+        total += push;
+    }
+    free(flow);
+    free(via);
+    free(queue);
+    return total;
+}
+
 /* Stage 2 evaluation of the system function (section 3.5): Y = 0 for a
  * lower-classified sample, 1 for an upper-classified one, Phi(x) for the
  * unclassified ones.  which = 1 evaluates Phi on every sample (plain Monte
@@ -451,6 +508,53 @@ static int above_global(const uint8_t* x, const void* user) {
     return or_phi_global(u->n_nodes, u->n_edges, u->eu, u->ev, u->level, x);
 }
 
+struct flow_user {
+    int n_nodes, n_edges, s, t, demand;
+    const int32_t *eu, *ev;
+};
+
+static int above_flow(const uint8_t* x, const void* user) {
+    const struct flow_user* u = (const struct flow_user*)user;
+    return or_maxflow_st(u->n_nodes, u->n_edges, u->eu, u->ev, u->s, u->t, x) >= u->demand;
+}
+
+/* Boundary search for the target max flow >= demand: the results are
+ * d-minimal path vectors (upper) and d-minimal cut vectors (lower). */
+int64_t or_boundary_flow(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int s,
+                         int t, int demand, int K, const uint8_t* x, int64_t Ns, uint8_t* out,
+                         uint8_t* side) {
+    struct flow_user u = {n_nodes, n_edges, s, t, demand, eu, ev};
+    int64_t evals = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : evals)
+    for (int64_t h = 0; h < Ns; ++h) {
+        int64_t e = 0;
+        memcpy(out + (size_t)h * n_edges, x + (size_t)h * n_edges, (size_t)n_edges);
+        side[h] = (uint8_t)boundary_search(n_edges, K, out + (size_t)h * n_edges, above_flow, &u, &e);
+        evals += e;
+    }
+    return evals;
+}
+
+/* Stage 2 evaluation for the max-flow target: as or_eval. */
+int64_t or_eval_flow(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int s, int t,
+                     int demand, const uint8_t* x, const uint8_t* flags, int64_t N, int which,
+                     uint8_t* Y) {
+    int64_t evaluated = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : evaluated)
+    for (int64_t h = 0; h < N; ++h) {
+        const uint8_t* xh = x + (size_t)h * n_edges;
+        if (which == 0 && (flags[h] & 1)) {
+            Y[h] = 0;
+        } else if (which == 0 && (flags[h] & 2)) {
+            Y[h] = 1;
+        } else {
+            Y[h] = (uint8_t)(or_maxflow_st(n_nodes, n_edges, eu, ev, s, t, xh) >= demand);
+            evaluated += 1;
+        }
+    }
+    return evaluated;
+}
+
 /* Boundary search for global connectivity at `level` (components = edges). */
 int64_t or_boundary_global(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev,
                            int level, int K, const uint8_t* x, int64_t Ns, uint8_t* out,
@@ -579,6 +683,23 @@ void bf_state_table_global(int n_nodes, int n_edges, const int32_t* eu, const in
         for (int64_t idx = 0; idx < (int64_t)total; ++idx) {
             index_to_state((uint64_t)idx, n_edges, K, x);
             table[idx] = (uint8_t)or_state_global(n_nodes, n_edges, eu, ev, x);
+        }
+        free(x);
+    }
+}
+
+/* Max flow of every one of the K^n states, capped at 255. */
+void bf_maxflow_table(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int s,
+                      int t, int K, uint8_t* table) {
+    uint64_t total = state_count(n_edges, K);
+#pragma omp parallel
+    {
+        uint8_t* x = (uint8_t*)malloc((size_t)n_edges);
+#pragma omp for schedule(static)
+        for (int64_t idx = 0; idx < (int64_t)total; ++idx) {
+            index_to_state((uint64_t)idx, n_edges, K, x);
+            int f = or_maxflow_st(n_nodes, n_edges, eu, ev, s, t, x);
+            table[idx] = (uint8_t)(f > 255 ? 255 : f);
         }
         free(x);
     }

@@ -3,8 +3,8 @@
 Each mutant is a copy of oracle/oracle.c with one plausible mistake planted
 (a swapped constant, an off-by-one, a flipped comparison, a dropped term, a
 wrong index).  It is compiled to a temporary library and the pin suites
-(test_oracle_pins.py, test_oracle_boundary.py, test_oracle_global.py) run
-against it in a subprocess; every mutant must make
+(test_oracle_pins.py, test_oracle_boundary.py, test_oracle_global.py,
+test_oracle_flow.py) run against it in a subprocess; every mutant must make
 at least one pin fail.  This shows that the pins constrain every part of the
 oracle, not only that the oracle passes them."""
 import concurrent.futures as cf
@@ -69,8 +69,14 @@ MUTANTS = {
                                   "return or_state_global(n_nodes, n_edges, eu, ev, x) > level;"),
     "global: node 0 not counted": ("    seen[0] = 1;\n    queue[tail++] = 0;",
                                    "    seen[0] = 1;\n    queue[tail++] = 0;\n    tail += 0 * head++;"),
+    "flow: reverse capacity ignores the flow": ("else if (ev[e] == u) { w = eu[e]; spare = x[e] + flow[e]; }",
+                                                "else if (ev[e] == u) { w = eu[e]; spare = x[e]; }"),
+    "flow: push sign flipped": ("if (from == eu[e]) flow[e] += push; else flow[e] -= push;",
+                                "if (from == eu[e]) flow[e] -= push; else flow[e] += push;"),
+    "flow: one augmenting path only": ("        total += push;\n    }", "        total += push;\n        break;\n    }"),
 }
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_boundary.py", "test_oracle_global.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_boundary.py", "test_oracle_global.py",
+             "test_oracle_flow.py"]
 
 
 def _run(name, old, new, tmp):
@@ -82,16 +88,21 @@ def _run(name, old, new, tmp):
     subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                     "-o", path_so, path_c, "-lm"], check=True, capture_output=True)
     env = dict(os.environ, RSR_ORACLE_LIB=path_so, OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest",
-                        *[os.path.join(ROOT, "tests", f) for f in PIN_FILES],
-                        "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env,
-                       capture_output=True, text=True, timeout=600)
+    # A mutant can also loop forever (a flow that never saturates): a pin that
+    # times out has caught it too.
+    try:
+        r = subprocess.run([sys.executable, "-m", "pytest",
+                            *[os.path.join(ROOT, "tests", f) for f in PIN_FILES],
+                            "-x", "-q", "-p", "no:cacheprovider", "--timeout", "20"],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    except subprocess.TimeoutExpired:
+        return name, "timeout"
     return name, r.returncode
 
 
 def test_every_mutant_is_killed():
     with tempfile.TemporaryDirectory() as tmp:
-        with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        with cf.ThreadPoolExecutor(max_workers=6) as ex:
             results = list(ex.map(lambda kv: _run(kv[0], kv[1][0], kv[1][1], tmp), MUTANTS.items()))
     survivors = [name for name, rc in results if rc == 0]
     assert not survivors, f"mutants not caught by any pin: {survivors}"
