@@ -65,7 +65,7 @@ typedef enum {
 enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
 enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2, RSR_MFMA_FP4 = 3 };  /* rsr_classify form */
 enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown which */
-enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2 };  /* rsr_system_desc kind */
+enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2, RSR_SYS_MAX_FLOW = 3 };  /* rsr_system_desc kind */
 
 /* Limits of this build. */
 #define RSR_MAX_K 16
@@ -101,15 +101,19 @@ typedef struct {
  *     the working edges connect every node but some single edge failure
  *     would disconnect them, 2 when every pair of nodes keeps two
  *     edge-disjoint paths (no bridge); Phi = 1 when that state is at least
- *     `level` (1 or 2) (sections 4.3 and 4.4).  source and sink are unused. */
+ *     `level` (1 or 2) (sections 4.3 and 4.4).  source and sink are unused.
+ *   RSR_SYS_MAX_FLOW: edge e carries up to x_e units of flow in either
+ *     direction; the system state is the maximum flow from source to sink,
+ *     and Phi = 1 when it is at least `level` (the demand d >= 1).  Its
+ *     reference states are the d-minimal path and cut vectors (section 2.2). */
 typedef struct {
-    int32_t kind;       /* RSR_SYS_ST_CONNECTIVITY or RSR_SYS_GLOBAL_CONNECTIVITY */
+    int32_t kind;       /* RSR_SYS_ST_CONNECTIVITY, _GLOBAL_CONNECTIVITY or _MAX_FLOW */
     int32_t n_nodes;    /* 2..RSR_MAX_NODES */
     int32_t n_edges;    /* = n, the number of components */
     int32_t K;          /* states per component */
     const int32_t* edge_u;  /* host [n_edges], node ids in [0, n_nodes) */
     const int32_t* edge_v;  /* host [n_edges] */
-    int32_t source, sink;   /* distinct node ids (s-t connectivity only) */
+    int32_t source, sink;   /* distinct node ids (unused for global connectivity) */
     int32_t level;
 } rsr_system_desc;
 
@@ -164,7 +168,10 @@ rsr_status rsr_refs_consistent(const rsr_refs* refs, int32_t* out);
 
 /* System function handle: copies the graph to the device.  EINVAL on a node
  * id out of range; for s-t connectivity on source == sink or level outside
- * 1..K-1; for global connectivity on level outside 1..2. */
+ * 1..K-1; for global connectivity on level outside 1..2; for max flow on
+ * source == sink or level outside 1..255.  EUNSUPPORTED when the per-sample
+ * search state of global connectivity or max flow exceeds 64 KB of LDS per
+ * four samples (about 2800 nodes at 4096 edges). */
 rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* desc, rsr_system** out);
 rsr_status rsr_system_destroy(rsr_system* sys);
 

@@ -17,6 +17,7 @@ RSR_AUTO, RSR_POPCOUNT, RSR_MFMA, RSR_MFMA_FP4 = 0, 1, 2, 3
 RSR_UNKNOWN_ONLY, RSR_ALL = 0, 1
 RSR_SYS_ST_CONNECTIVITY = 1
 RSR_SYS_GLOBAL_CONNECTIVITY = 2
+RSR_SYS_MAX_FLOW = 3
 RSR_MAX_K = 16
 RSR_MAX_BITS = 4096
 RSR_MAX_NODES = 4096

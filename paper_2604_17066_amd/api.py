@@ -113,14 +113,16 @@ class Refs:
 
 
 class System:
-    """rsr_system: s-t connectivity of a graph at a level (kind "st"), or
-    global connectivity at level 1 (connected) or 2 (two-edge-connected)
-    (kind "global")."""
+    """rsr_system: s-t connectivity of a graph at a level (kind "st"), global
+    connectivity at level 1 (connected) or 2 (two-edge-connected) (kind
+    "global"), or max s-t flow >= level with capacities = states (kind
+    "flow")."""
 
     def __init__(self, ctx, graph, K=2, level=1, kind="st"):
         eu = np.ascontiguousarray(graph["edge_u"], dtype=np.int32)
         ev = np.ascontiguousarray(graph["edge_v"], dtype=np.int32)
-        code = {"st": A.RSR_SYS_ST_CONNECTIVITY, "global": A.RSR_SYS_GLOBAL_CONNECTIVITY}[kind]
+        code = {"st": A.RSR_SYS_ST_CONNECTIVITY, "global": A.RSR_SYS_GLOBAL_CONNECTIVITY,
+                "flow": A.RSR_SYS_MAX_FLOW}[kind]
         desc = A.rsr_system_desc(
             code, int(graph["n_nodes"]), eu.size, int(K),
             eu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

@@ -261,6 +261,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_boundary_global(
 }  // namespace
 
 size_t boundary_lds_bytes(const rsr_system* sys) {
+    if (sys->kind == RSR_SYS_MAX_FLOW) return flow_lds_bytes(sys);
     const int n_nodes = sys->n_nodes, n_edges = sys->n_edges;
     size_t per_wave;
     if (sys->kind == RSR_SYS_GLOBAL_CONNECTIVITY) {
@@ -281,6 +282,8 @@ hipError_t launch_boundary(hipStream_t st, const rsr_system* sys, const uint32_t
     int64_t blocks = (n_pick + kBoundaryWaves - 1) / kBoundaryWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
+    if (sys->kind == RSR_SYS_MAX_FLOW)
+        return launch_boundary_flow(st, sys, xs, N, d_pick, n_pick, d_rows, d_side, grid_cap);
     const size_t lds = boundary_lds_bytes(sys);
     if (sys->kind == RSR_SYS_GLOBAL_CONNECTIVITY)
         hipLaunchKernelGGL(k_boundary_global, dim3(static_cast<unsigned>(blocks)),

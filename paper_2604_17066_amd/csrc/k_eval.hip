@@ -198,6 +198,8 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
     const int64_t need = (seg.total + kWavesPerBfsBlock - 1) / kWavesPerBfsBlock;
     int blocks = static_cast<int>(need < grid_blocks ? need : grid_blocks);
     if (blocks < 1) blocks = 1;
+    if (sys->kind == RSR_SYS_MAX_FLOW)
+        return launch_flow_eval(st, sys, seg, d_list, d_count, which, d_n_evaluated, grid_blocks);
     if (sys->kind == RSR_SYS_GLOBAL_CONNECTIVITY) {
         const size_t lds = sizeof(uint32_t) *
             (static_cast<size_t>(sys->n_edges) +

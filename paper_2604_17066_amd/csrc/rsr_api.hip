@@ -487,9 +487,11 @@ rsr_status rsr_refs_destroy(rsr_refs* refs) {
 rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system** out) {
     if (!ctx || !out || !d) return RSR_EINVAL;
     *out = nullptr;
-    if (d->kind != RSR_SYS_ST_CONNECTIVITY && d->kind != RSR_SYS_GLOBAL_CONNECTIVITY)
+    if (d->kind != RSR_SYS_ST_CONNECTIVITY && d->kind != RSR_SYS_GLOBAL_CONNECTIVITY &&
+        d->kind != RSR_SYS_MAX_FLOW)
         return fail(ctx, RSR_EINVAL, "unknown system kind");
     const bool global = d->kind == RSR_SYS_GLOBAL_CONNECTIVITY;
+    const bool flow = d->kind == RSR_SYS_MAX_FLOW;
     if (d->n_nodes < 2 || d->n_edges <= 0 || d->K < 2 || !d->edge_u || !d->edge_v)
         return fail(ctx, RSR_EINVAL, "bad graph size or NULL edge arrays");
     if (d->n_nodes > RSR_MAX_NODES || d->K > RSR_MAX_K ||
@@ -506,8 +508,15 @@ rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system*
         if (d->source < 0 || d->source >= d->n_nodes || d->sink < 0 || d->sink >= d->n_nodes ||
             d->source == d->sink)
             return fail(ctx, RSR_EINVAL, "source/sink out of range or equal");
-        if (d->level < 1 || d->level > d->K - 1)
-            return fail(ctx, RSR_EINVAL, "level not in 1..K-1");
+        if (flow ? (d->level < 1 || d->level > 255) : (d->level < 1 || d->level > d->K - 1))
+            return fail(ctx, RSR_EINVAL, flow ? "demand not in 1..255" : "level not in 1..K-1");
+        if (flow) {
+            // Edge list plus four waves' marks, parents, capacities and flows in 64 KB.
+            const int64_t words = d->n_edges + 4ll * (((d->n_nodes + 31) >> 5) + ((d->n_nodes + 1) >> 1) +
+                                                       3 * ((d->n_edges + 3) >> 2));
+            if (words * 4 > 64 * 1024)
+                return fail(ctx, RSR_EUNSUPPORTED, "graph too large for the max-flow search");
+        }
     }
     std::vector<uint32_t> packed(d->n_edges);
     for (int e = 0; e < d->n_edges; ++e) {

@@ -194,6 +194,13 @@ hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
                       uint64_t* d_n_evaluated, int grid_blocks);
 hipError_t launch_fill_u64(hipStream_t st, uint64_t* p, int64_t count, uint64_t value);
 size_t boundary_lds_bytes(const rsr_system* sys);
+size_t flow_lds_bytes(const rsr_system* sys);
+hipError_t launch_flow_eval(hipStream_t st, const rsr_system* sys, const SegSrc& seg,
+                            const int32_t* d_list, const uint64_t* d_count, int which,
+                            uint64_t* d_n_evaluated, int grid_blocks);
+hipError_t launch_boundary_flow(hipStream_t st, const rsr_system* sys, const uint32_t* xs,
+                                int64_t N, const int64_t* d_pick, int64_t n_pick, uint8_t* d_rows,
+                                uint8_t* d_side, int grid_cap);
 // rsr_refs_create; without matrix_operands the MFMA fragments are not built
 // (the handle then serves the popcount and cascade forms only).
 rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower, int64_t R_L,
