@@ -181,6 +181,7 @@ def main():
         extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps)
         extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
         extra["global_connectivity"] = global_leg(ctx)
+        extra["max_flow"] = flow_leg(ctx)
 
     out = {
         "metric": "dominance tests/s (samples x reference states), whole Stage-2 step",
@@ -405,6 +406,60 @@ def global_leg(ctx):
         f"{stage1_s:.2f} s; stage 2 (N=1e6) {stage2_ms:.2f} ms, P={est['P']:.5f}, "
         f"p_u={est['p_u']:.3e}; boundary search {out['level1_boundary_searches_per_s']:.3g}/s "
         f"(level 1), {out['level2_boundary_searches_per_s']:.3g}/s (level 2)")
+    return out
+
+
+def flow_leg(ctx):
+    """Single-OD maximum flow on graph2 with edge capacities {0, 1, 2} (the
+    three-state model of the multi-state workload), demand d = 2: Stage 1 from
+    empty reference sets (the rows are d-minimal path and cut vectors), Stage 2
+    on 1e6 samples with them, plain Monte Carlo (max flow on every sample) for
+    comparison, and the boundary-search rate."""
+    import time as _t
+    import torch
+    import paper_2604_17066_amd as R
+    import workloads as WL
+    cfg = WL.configs.multi(N=1, R_per_level=4)
+    d = 2
+    model = R.Model(ctx, cfg["p"])
+    system = R.System(ctx, cfg["graph"], K=3, level=d, kind="flow")
+    R.stage1(ctx, model, system, 10_000, 64, 1e-4, 200, 3, 1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    lo, up, info = R.stage1(ctx, model, system, 100_000, 4096, 1e-4, 50_000, 200, 11)
+    stage1_s = _t.perf_counter() - t0
+    refs = R.Refs(ctx, cfg["n"], 3, lo, up)
+    N2 = 1_000_000
+    est, buf = R.stage2(ctx, model, refs, system, N2, 99)
+    torch.cuda.synchronize()
+    reps = 5
+    t1 = _t.perf_counter()
+    for _ in range(reps):
+        est, buf = R.stage2(ctx, model, refs, system, N2, 99, buffers=buf)
+    torch.cuda.synchronize()
+    stage2_ms = (_t.perf_counter() - t1) * 1e3 / reps
+    t2 = _t.perf_counter()
+    Y = R.rsr_eval_unknown(ctx, system, buf.samples, N2, None, which=R.RSR_ALL)
+    torch.cuda.synchronize()
+    plain_ms = (_t.perf_counter() - t2) * 1e3
+    plain_P = float(Y.float().mean().item())
+    N = 1 << 16
+    picks = torch.arange(0, N, dtype=torch.int64, device=ctx.device)
+    rows, side = R.rsr_boundary_search(ctx, system, buf.samples, N, picks)
+    torch.cuda.synchronize()
+    t3 = _t.perf_counter()
+    R.rsr_boundary_search(ctx, system, buf.samples, N, picks, rows=rows, side=side)
+    torch.cuda.synchronize()
+    searches = N / (_t.perf_counter() - t3)
+    out = {"workload": "max s-t flow >= 2 on graph2 (119 nodes / 295 edges), capacities {0,1,2} "
+                       "with (p0,p1,p2) = reversed Dirichlet(8,2,1)",
+           "stage1_s": stage1_s, "stage1": info, "rows": len(lo) + len(up),
+           "stage2_ms_N1e6": stage2_ms, "P": est["P"], "p_u": est["p_u"], "se": est["se"],
+           "plain_mc_ms_N1e6": plain_ms, "plain_mc_P": plain_P,
+           "boundary_searches_per_s": searches}
+    log(f"max flow >= {d}: stage 1 {info['iterations']} iterations, {len(lo) + len(up)} rows, "
+        f"{stage1_s:.2f} s, p_u {info['p_u']:.2e}; stage 2 (N=1e6) {stage2_ms:.2f} ms, "
+        f"P={est['P']:.5f}; plain MC {plain_ms:.2f} ms; boundary search {searches:.3g}/s")
     return out
 
 
