@@ -17,7 +17,10 @@
 //     grid y = chunk) to keep the GPU busy; a chunk that finds a match ORs it
 //     into the sample's match word, and k_casc_resolve then writes flags and
 //     compacts the still undecided samples.  A round whose rows do not warrant
-//     a split runs k_casc_fused on the compact buffer instead.
+//     a split runs k_casc_fused on the compact buffer instead.  With
+//     shape.mfma_tail the split rounds' tests run in the FP4 matrix-core form
+//     (k_casc_mfma of k_dom_mfma.hip), which makes more tests per second once
+//     the undecided samples have to be tested against many rows.
 //   the last round flags every remaining sample as unclassified.
 //
 // Compaction reserves output slots with one atomic per block (wave ballots,
@@ -317,11 +320,17 @@ hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
                                    u1, dst, dst_idx, dst_match, cb.stride, dst_count, last ? 1 : 0);
             e = hipGetLastError();
         } else {
-            const int64_t bx = blocks_for(kBlock, grid_cap / chunks > 0 ? grid_cap / chunks : 1);
-            hipLaunchKernelGGL((k_casc_test<W>), dim3(static_cast<unsigned>(bx), chunks), dim3(kBlock),
-                               0, st, csrc, cb.stride, src_count, refs->W, refs->d_lower_nbits, l0,
-                               l1, refs->d_upper_bits, u0, u1, const_cast<uint32_t*>(src_match));
-            e = hipGetLastError();
+            if (shape.mfma_tail && refs->KS4 > 0) {
+                e = launch_casc_mfma(st, refs, csrc, cb.stride, src_count, N, l0, l1, u0, u1, chunks,
+                                     grid_cap, const_cast<uint32_t*>(src_match));
+            } else {
+                const int64_t bx = blocks_for(kBlock, grid_cap / chunks > 0 ? grid_cap / chunks : 1);
+                hipLaunchKernelGGL((k_casc_test<W>), dim3(static_cast<unsigned>(bx), chunks),
+                                   dim3(kBlock), 0, st, csrc, cb.stride, src_count, refs->W,
+                                   refs->d_lower_nbits, l0, l1, refs->d_upper_bits, u0, u1,
+                                   const_cast<uint32_t*>(src_match));
+                e = hipGetLastError();
+            }
             if (e == hipSuccess) {
                 hipLaunchKernelGGL(k_casc_resolve, dim3(static_cast<unsigned>(blocks_for(kBlock, grid_cap))),
                                    dim3(kBlock), 0, st, seg, csrc, cb.stride, src_idx, src_count,

@@ -246,6 +246,48 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
     fold<MT, COUNT, FP4>(prev, acc_out);
 }
 
+// Sample operand of the wave's MT sample tiles (samples wbase .. +16 MT of
+// the word-major array xs with row stride `stride`; those at or past `count`,
+// or whose `done` word is set, are not valid).
+//   int8: bytes 16*grp .. +15 of k-step s are packed bits 64 s + 16 grp .. +15,
+//         i.e. half (grp & 1) of word 2 s + (grp >> 1).
+//   FP4:  nibbles 32*grp .. +31 of k-step s are bits 128 s + 32 grp .. +31,
+//         i.e. the whole word 4 s + grp.
+// The reference fragments use the same positions, so A and B agree on the k
+// of every operand element.
+template <int KS, int MT, bool FP4>
+__device__ __forceinline__ void load_samples(const uint32_t* __restrict__ xs, int64_t stride,
+                                             int64_t count, int W, int64_t wbase, int col, int grp,
+                                             const uint32_t* __restrict__ done, v4i (&bf)[MT][KS],
+                                             bool (&valid)[MT]) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int64_t h = wbase + 16 * t + col;
+        valid[t] = h < count && (!done || done[h] == 0u);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            v4i f;
+            if constexpr (FP4) {
+                const int w = 4 * s + grp;
+                const uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * stride + h] : 0u;
+                f.x = expand8_fp4(bits & 0xFFu);
+                f.y = expand8_fp4((bits >> 8) & 0xFFu);
+                f.z = expand8_fp4((bits >> 16) & 0xFFu);
+                f.w = expand8_fp4(bits >> 24);
+            } else {
+                const int w = 2 * s + (grp >> 1);
+                uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * stride + h] : 0u;
+                bits = (bits >> (16 * (grp & 1))) & 0xFFFFu;
+                f.x = expand4(bits & 0xFu);
+                f.y = expand4((bits >> 4) & 0xFu);
+                f.z = expand4((bits >> 8) & 0xFu);
+                f.w = expand4(bits >> 12);
+            }
+            bf[t][s] = f;
+        }
+    }
+}
+
 template <int KS, int MT, bool COUNT, bool FP4>
 __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     const uint32_t* __restrict__ xs, int64_t N, int W, const v4i* __restrict__ low_frag,
@@ -259,39 +301,9 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     const int col = lane & 15, grp = lane >> 4;
     const int64_t wbase = (static_cast<int64_t>(blockIdx.x) * kWaves + wave) * (16 * MT);
 
-    // Sample operand.  int8: bytes 16*grp .. +15 of k-step s are packed bits
-    // 64 s + 16 grp .. +15, i.e. half (grp & 1) of word 2 s + (grp >> 1).
-    // FP4: nibbles 32*grp .. +31 of k-step s are bits 128 s + 32 grp .. +31,
-    // i.e. the whole word 4 s + grp.  The reference fragments use the same
-    // positions, so A and B agree on the k of every operand element.
     v4i bf[MT][KS];
     bool valid[MT];
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
-        const int64_t h = wbase + 16 * t + col;
-        valid[t] = h < N;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            v4i f;
-            if constexpr (FP4) {
-                const int w = 4 * s + grp;
-                const uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * N + h] : 0u;
-                f.x = expand8_fp4(bits & 0xFFu);
-                f.y = expand8_fp4((bits >> 8) & 0xFFu);
-                f.z = expand8_fp4((bits >> 16) & 0xFFu);
-                f.w = expand8_fp4(bits >> 24);
-            } else {
-                const int w = 2 * s + (grp >> 1);
-                uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * N + h] : 0u;
-                bits = (bits >> (16 * (grp & 1))) & 0xFFFFu;
-                f.x = expand4(bits & 0xFu);
-                f.y = expand4((bits >> 4) & 0xFu);
-                f.z = expand4((bits >> 8) & 0xFu);
-                f.w = expand4(bits >> 12);
-            }
-            bf[t][s] = f;
-        }
-    }
+    load_samples<KS, MT, FP4>(xs, N, N, W, wbase, col, grp, nullptr, bf, valid);
 
     int accL[MT], accU[MT];  // 0 = no match yet in both modes
     bool none[MT];
@@ -371,6 +383,93 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     }
 }
 
+// One chunk of a split LABEL round of the cascade (k_cascade.hip) in the FP4
+// form: the compacted undecided samples (word-major, row stride cstride, their
+// number on the device) against the reference tiles of chunk blockIdx.y of
+// the round's tile ranges, both sides; a match is ORed into the sample's
+// match word (bit0 lower, bit1 upper).  The tile ranges may reach a few rows
+// outside the round's rows: on a consistent reference set any match decides
+// the label, so testing a row early or twice changes nothing.
+template <int KS, int MT>
+__global__ __launch_bounds__(kBlock) void k_casc_mfma(
+    const uint32_t* __restrict__ csrc, int64_t cstride,
+    const unsigned long long* __restrict__ src_count, int W, const v4i* __restrict__ low_frag,
+    const v4i* __restrict__ low_c, int lt0, int lt1, const v4i* __restrict__ up_frag,
+    const v4i* __restrict__ up_c, int ut0, int ut1, uint32_t* __restrict__ match) {
+    __shared__ v4i lds[2 * tiles_per_stage<KS>() * (KS * 64 + 4)];
+    __shared__ int vote[kWaves];
+    const int64_t total = static_cast<int64_t>(*src_count);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int chunks = gridDim.y, c = blockIdx.y;
+    const int nL = lt1 - lt0, nU = ut1 - ut0;
+    const int cl0 = lt0 + static_cast<int>((static_cast<int64_t>(nL) * c) / chunks);
+    const int cl1 = lt0 + static_cast<int>((static_cast<int64_t>(nL) * (c + 1)) / chunks);
+    const int cu0 = ut0 + static_cast<int>((static_cast<int64_t>(nU) * c) / chunks);
+    const int cu1 = ut0 + static_cast<int>((static_cast<int64_t>(nU) * (c + 1)) / chunks);
+    constexpr int kFragV4 = KS * 64;
+    constexpr int64_t kPerBlock = static_cast<int64_t>(kWaves) * 16 * MT;
+    // Block-uniform loop (the passes synchronise the block).
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kPerBlock; b0 < total;
+         b0 += static_cast<int64_t>(gridDim.x) * kPerBlock) {
+        const int64_t wbase = b0 + static_cast<int64_t>(wave) * 16 * MT;
+        v4i bf[MT][KS];
+        bool valid[MT];
+        load_samples<KS, MT, true>(csrc, cstride, total, W, wbase, col, grp, match, bf, valid);
+        int accL[MT], accU[MT];
+        bool none[MT], lowered[MT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            accL[t] = accU[t] = 0;
+            none[t] = false;
+        }
+        mfma_pass<KS, MT, false, true>(bf, low_frag + static_cast<int64_t>(cl0) * kFragV4,
+                                       low_c + static_cast<int64_t>(cl0) * 4, cl1 - cl0, lds, accL,
+                                       none, valid, vote);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            int m = accL[t];
+            m = min(m, __shfl_xor(m, 16));
+            m = min(m, __shfl_xor(m, 32));
+            lowered[t] = m < 0;
+        }
+        mfma_pass<KS, MT, false, true>(bf, up_frag + static_cast<int64_t>(cu0) * kFragV4,
+                                       up_c + static_cast<int64_t>(cu0) * 4, cu1 - cu0, lds, accU,
+                                       lowered, valid, vote);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            int m = accU[t];
+            m = min(m, __shfl_xor(m, 16));
+            m = min(m, __shfl_xor(m, 32));
+            const uint32_t bits = (lowered[t] ? 1u : 0u) | (m < 0 ? 2u : 0u);
+            if (grp == 0 && valid[t] && bits)
+                atomicOr(&match[wbase + 16 * t + col], bits);
+        }
+    }
+}
+
+template <int KS>
+hipError_t launch_casc_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* csrc,
+                          int64_t cstride, const unsigned long long* src_count, int64_t max_count,
+                          int l0, int l1, int u0, int u1, int chunks, int grid_cap,
+                          uint32_t* match) {
+    constexpr int MT = sample_tiles<KS, true>();
+    const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
+    int64_t bx = (max_count + per_block - 1) / per_block;
+    const int64_t cap = grid_cap / chunks > 0 ? grid_cap / chunks : 1;
+    if (bx > cap) bx = cap;
+    if (bx < 1) bx = 1;
+    hipLaunchKernelGGL((k_casc_mfma<KS, MT>), dim3(static_cast<unsigned>(bx), chunks),
+                       dim3(kBlock), 0, st, csrc, cstride, src_count, refs->W,
+                       reinterpret_cast<const v4i*>(refs->d_lower_frag4),
+                       reinterpret_cast<const v4i*>(refs->d_lower_cinit4), l0 / 16, (l1 + 15) / 16,
+                       reinterpret_cast<const v4i*>(refs->d_upper_frag4),
+                       reinterpret_cast<const v4i*>(refs->d_upper_cinit4), u0 / 16, (u1 + 15) / 16,
+                       match);
+    return hipGetLastError();
+}
+
 template <int KS, bool FP4>
 hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
                      int mode, uint8_t* flags, uint32_t* match) {
@@ -413,6 +512,21 @@ hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t*
         RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
         RSR_KS_CASE(11) RSR_KS_CASE(12) RSR_KS_CASE(13) RSR_KS_CASE(14) RSR_KS_CASE(15)
         RSR_KS_CASE(16) RSR_KS_CASE(17) RSR_KS_CASE(18) RSR_KS_CASE(19) RSR_KS_CASE(20)
+#undef RSR_KS_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_casc_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* csrc,
+                            int64_t cstride, const unsigned long long* src_count, int64_t max_count,
+                            int l0, int l1, int u0, int u1, int chunks, int grid_cap,
+                            uint32_t* match) {
+    switch (refs->KS4) {
+#define RSR_KS_CASE(k) \
+    case k: return launch_casc_ks<k>(st, refs, csrc, cstride, src_count, max_count, l0, l1, u0, \
+                                     u1, chunks, grid_cap, match);
+        RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
+        RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
 #undef RSR_KS_CASE
         default: return hipErrorInvalidValue;
     }

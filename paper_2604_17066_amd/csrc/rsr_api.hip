@@ -599,10 +599,14 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         cb.match[1] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 3 * N);
         cb.stride = N;
         cb.counters = ctx->ws.casc_counters;
+        // The automatic form runs the split rounds in the FP4 matrix-core form
+        // when the handle has its operands; the popcount form stays popcount.
+        rsr::CascadeShape shape;
+        shape.mfma_tail = form == RSR_AUTO && refs->KS4 > 0;
         RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0));
         RSR_HIP(ctx, rsr::launch_dom_cascade(ctx->stream, refs,
                                              rsr::single_src(d_samples, N, d_flags, nullptr), cb,
-                                             rsr::CascadeShape{}, ctx->cu_count * 8));
+                                             shape, ctx->cu_count * 8));
         return RSR_OK;
     }
     if (matrix)

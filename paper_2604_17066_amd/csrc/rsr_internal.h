@@ -176,6 +176,7 @@ struct CascadeShape {
     int first = 16;
     int growth = 4;
     int split_rows = 128;
+    bool mfma_tail = false;  // split rounds in the FP4 matrix-core form (needs refs->KS4 > 0)
 };
 
 // Kernel launchers (each returns the hipError_t of the launch).
@@ -187,6 +188,11 @@ hipError_t launch_dom_cascade(hipStream_t st, const rsr_refs* refs, const SegSrc
                               const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap);
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
                            int64_t N, int mode, bool fp4, uint8_t* d_flags, uint32_t* d_match);
+// Split-round test of the cascade in the FP4 matrix-core form (k_dom_mfma.hip).
+hipError_t launch_casc_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* csrc,
+                            int64_t cstride, const unsigned long long* src_count, int64_t max_count,
+                            int l0, int l1, int u0, int u1, int chunks, int grid_cap,
+                            uint32_t* match);
 hipError_t launch_label(hipStream_t st, const SegSrc& seg, int32_t* d_list, uint64_t* d_counter,
                         int grid_cap);
 hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,

@@ -27,7 +27,7 @@
 
 namespace {
 
-enum Choice { kCascade = 0, kBitsPerJob = 1, kMfmaPerJob = 2 };
+enum Choice { kCascade = 0, kBitsPerJob = 1, kMfmaPerJob = 2, kMfma4PerJob = 3 };
 
 struct Segment {
     const rsr_refs* refs = nullptr;
@@ -131,9 +131,9 @@ hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice ch
     }
     for (int j : s.jobs) {
         const rsr_job& jb = p->jobs[j];
-        hipError_t e = choice == kMfmaPerJob
+        hipError_t e = choice == kMfmaPerJob || choice == kMfma4PerJob
                            ? rsr::launch_dom_mfma(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
-                                                  false, jb.d_flags, nullptr)
+                                                  choice == kMfma4PerJob, jb.d_flags, nullptr)
                            : rsr::launch_dom_bits(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
                                                   jb.d_flags, nullptr);
         if (e != hipSuccess) return e;
@@ -163,8 +163,10 @@ hipError_t enqueue_rest(const rsr_plan* p, int si, hipStream_t st) {
     return e;
 }
 
-// Times each candidate classification of one segment on its own samples
-// (drawn once) and keeps the fastest.
+// Times candidate classifications of one segment on its own samples (drawn
+// once) and keeps the fastest.  For a consistent reference set the split-round
+// form (popcount or FP4) is chosen first on the default cascade shape, then
+// the shape with that form; otherwise the per-job forms are compared.
 rsr_status tune_segment(rsr_plan* p, int si) {
     Segment& s = p->segs[si];
     rsr_ctx* ctx = p->ctx;
@@ -172,42 +174,53 @@ rsr_status tune_segment(rsr_plan* p, int si) {
         Choice c;
         rsr::CascadeShape shape;
     };
-    std::vector<Cand> cands;
-    if (s.refs->consistent) {
-        const int firsts[] = {8, 16, 32, 64};
-        const int growths[] = {4, 8};
-        const int splits[] = {64, 256};
-        for (int f : firsts)
-            for (int g : growths)
-                for (int sp : splits) cands.push_back({kCascade, rsr::CascadeShape{f, g, sp}});
-    }
-    if (!s.refs->consistent) {
-        cands.push_back({kBitsPerJob, rsr::CascadeShape{}});
-        if (s.refs->KS > 0) cands.push_back({kMfmaPerJob, rsr::CascadeShape{}});
-    }
     PLAN_HIP(ctx, enqueue_sample(p, si, p->cap));
     hipEvent_t a, b;
     PLAN_HIP(ctx, hipEventCreate(&a));
     PLAN_HIP(ctx, hipEventCreate(&b));
     float best = 1e30f;
-    for (const Cand& c : cands) {
-        PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));  // warm-up
-        PLAN_HIP(ctx, hipEventRecord(a, p->cap));
-        for (int rep = 0; rep < 2; ++rep) PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));
-        PLAN_HIP(ctx, hipEventRecord(b, p->cap));
-        PLAN_HIP(ctx, hipEventSynchronize(b));
-        float ms = 0.0f;
-        PLAN_HIP(ctx, hipEventElapsedTime(&ms, a, b));
-        if (ms < best) {
-            best = ms;
-            s.choice = c.c;
-            s.shape = c.shape;
+    auto trial = [&](const std::vector<Cand>& cands) -> rsr_status {
+        for (const Cand& c : cands) {
+            PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));  // warm-up
+            PLAN_HIP(ctx, hipEventRecord(a, p->cap));
+            for (int rep = 0; rep < 2; ++rep)
+                PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));
+            PLAN_HIP(ctx, hipEventRecord(b, p->cap));
+            PLAN_HIP(ctx, hipEventSynchronize(b));
+            float ms = 0.0f;
+            PLAN_HIP(ctx, hipEventElapsedTime(&ms, a, b));
+            if (ms < best) {
+                best = ms;
+                s.choice = c.c;
+                s.shape = c.shape;
+            }
         }
+        return RSR_OK;
+    };
+    rsr_status st = RSR_OK;
+    if (s.refs->consistent) {
+        std::vector<Cand> forms = {{kCascade, rsr::CascadeShape{}}};
+        if (s.refs->KS4 > 0) forms.push_back({kCascade, rsr::CascadeShape{16, 4, 128, true}});
+        st = trial(forms);
+        const bool tail = s.shape.mfma_tail;
+        std::vector<Cand> shapes;
+        const int firsts[] = {8, 16, 32, 64};
+        const int growths[] = {4, 8};
+        const int splits[] = {64, 256};
+        for (int f : firsts)
+            for (int g : growths)
+                for (int sp : splits) shapes.push_back({kCascade, rsr::CascadeShape{f, g, sp, tail}});
+        if (st == RSR_OK) st = trial(shapes);
+    } else {
+        std::vector<Cand> forms = {{kBitsPerJob, rsr::CascadeShape{}}};
+        if (s.refs->KS > 0) forms.push_back({kMfmaPerJob, rsr::CascadeShape{}});
+        if (s.refs->KS4 > 0) forms.push_back({kMfma4PerJob, rsr::CascadeShape{}});
+        st = trial(forms);
     }
     s.tuned_ms = best / 2.0f;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    return RSR_OK;
+    return st;
 }
 
 void free_plan(rsr_plan* p) {

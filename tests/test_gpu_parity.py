@@ -57,12 +57,14 @@ def test_sample_bit_identical(rsr_ctx, n, K, N, first, stream):
 
 # ------------------------------------------------------------- classifier ----
 
-FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4)
+FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO)
 
 
 def _classify_both(ctx, cfg, N, lower, upper, level=1):
-    """Both kernel forms in both modes; returns {form: (label flags, count
-    flags, match counts)} and the oracle's answers."""
+    """Every kernel form (and the automatic choice, whose LABEL mode on
+    consistent rows is the cascade with FP4 split rounds) in both modes;
+    returns {form: (label flags, count flags, match counts)} and the oracle's
+    answers."""
     n, K = cfg["n"], cfg["K"]
     p = cfg["p"]
     m, xs = _sample(ctx, p, cfg["seed"], cfg["stream"], 0, N)
@@ -325,3 +327,24 @@ def test_classify_forms_agree_and_deterministic(rsr_ctx):
                       R.RSR_MFMA_FP4, R.RSR_POPCOUNT)]
     for r in runs[1:]:
         np.testing.assert_array_equal(r, runs[0])
+
+
+def test_cascade_fp4_split_rounds_large_rows(rsr_ctx):
+    """The 1250-edge graph (40 words per row) with 1e4 path / cut rows: the
+    automatic LABEL cascade runs its split rounds in the FP4 form; labels equal
+    the popcount cascade's and the oracle's."""
+    sd = WL.configs.batched(n_scen=1, N=1, graphs=[7], ref_scale=0.05)
+    sys_ = sd["systems"][0]
+    n = sys_["n"]
+    p = sd["jobs"][0]["p"]
+    N = 3000
+    m, xs = _sample(rsr_ctx, p, 3, 0, 0, N)
+    refs = R.Refs(rsr_ctx, n, 2, sys_["lower"], sys_["upper"])
+    assert refs.consistent
+    auto = _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO))
+    pop = _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT))
+    x = oracle.sample(p, 3, 0, 0, N)
+    want, _, _ = oracle.classify(sys_["lower"], sys_["upper"], x, mode=0)
+    print("rows", refs.R_L, refs.R_U, "unclassified", int((want == 0).sum()))
+    np.testing.assert_array_equal(pop, want)
+    np.testing.assert_array_equal(auto, want)
