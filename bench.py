@@ -36,7 +36,7 @@ MFMA_FP4_PEAK_FLOPS = 10.1e15
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
     "mfma": (433.88 + 0.95) * 2 ** 20,
-    "mfma_fp4": (222.55 + 0.95) * 2 ** 20,
+    "mfma_fp4": (227.36 + 0.95) * 2 ** 20,
 }
 
 
@@ -55,6 +55,9 @@ def main():
     ap.add_argument("--form", default="auto", choices=["auto", "popcount", "mfma", "mfma_fp4"])
     ap.add_argument("--skip-legs", action="store_true",
                     help="only the graph2 step (no scaling / multi-state / batched legs)")
+    ap.add_argument("--only-legs", default="", metavar="LIST",
+                    help="comma-separated legs (scaling, multi, batched, stage1, global, flow) to "
+                         "run alone, without the step; prints their results as one JSON line")
     ap.add_argument("--batched-scale", type=float, default=0.25,
                     help="reference rows of the batched workload, as a fraction of its sizes")
     ap.add_argument("--batched-reps", type=int, default=3)
@@ -70,6 +73,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {args.copy_calibration} MiB x 4")
+        return
+    if args.only_legs:
+        import paper_2604_17066_amd as R
+        ctx = R.Context(0)
+        runs = {"scaling": lambda: scaling_leg(ctx, 5), "multi": lambda: multi_leg(ctx, 5),
+                "batched": lambda: batched_leg(ctx, args.batched_scale, args.batched_reps),
+                "stage1": lambda: stage1_leg(ctx, False), "global": lambda: global_leg(ctx),
+                "flow": lambda: flow_leg(ctx)}
+        print(json.dumps({name: runs[name]() for name in args.only_legs.split(",")}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
