@@ -118,18 +118,48 @@ constexpr int tiles_per_stage() {
 
 // Sample tiles per wave: B fragments take MT * KS * 4 VGPRs, and with the two
 // accumulator sets of the pipelined fold everything must fit 256 VGPRs (two
-// waves per SIMD) without spilling.  For KS = 5 (up to 320 bits, the 295-edge
-// workloads) four tiles measure faster than five: a block then covers 512
-// samples, and 10^6 samples make 7.6 rounds of blocks over 256 CUs instead of
-// 6.1, so the last, partly idle round costs less.
+// waves per SIMD) without spilling.  This is the largest count that fits at
+// each width (the FP4 instruction's 8-register operand slots raise the count
+// a little); more tiles per wave means fewer LDS reads per matrix product.
 template <int KS, bool FP4>
 constexpr int sample_tiles() {
-    // FP4: the instruction's 8-register operand slots raise the count a
-    // little; two tiles from KS = 9 on avoid spilling.  KS = 3 (up to 384 bits,
-    // the 295-edge workloads) takes four for the same reason as int8 KS = 5.
-    if (FP4 && KS == 3) return 4;
-    if (FP4 && KS >= 9) return 2;
-    return KS <= 2 ? 8 : KS == 3 ? 7 : KS == 4 ? 6 : KS == 5 ? 4 : (KS >= 30 ? 1 : 30 / KS);
+    if (FP4 && KS == 3) return 8;
+    if (FP4 && KS >= 9) return 3;
+    return KS <= 2 ? 8 : KS == 3 ? 7 : KS == 4 ? 6 : KS == 5 ? 5 : KS <= 10 ? 30 / KS
+                                                                   : KS <= 13 ? 3 : 2;
+}
+
+// A smaller count also built for the widths of the 295-edge workloads (int8
+// KS = 5, FP4 KS = 3), or 0.  One block fills a CU, so the grid runs in
+// ceil(blocks / CUs) rounds and the last one may be mostly idle: at 10^6
+// samples int8 with five tiles takes 7 rounds against 8 of four tiles, one of
+// them 10 % full, and FP4 with eight tiles 4 rounds against 8.
+template <int KS, bool FP4>
+constexpr int sample_tiles_alt() {
+    return (FP4 && KS == 3) || (!FP4 && KS == 5) ? 4 : 0;
+}
+
+// Tile count of the split-round kernel (FP4), which also holds the lowered
+// flags and the compacted-sample indexing: the largest count that does not
+// spill at each width, except KS = 10, where two tiles with a small spill
+// measure faster than one.
+template <int KS>
+constexpr int casc_sample_tiles() {
+    return KS <= 2 ? 8 : KS == 3 ? 4 : KS == 4 ? 6 : KS == 5 ? 3 : KS == 6 ? 4 : KS <= 8 ? 3 : 2;
+}
+
+// Whether the smaller count `alt` finishes N samples sooner than `mt`: a wave
+// of MT tiles takes time about proportional to MT, so the cost of a count is
+// MT times the rounds of blocks it needs over `cus` CUs; ties go to the larger
+// count, whose staged reference tiles serve more samples.
+inline bool prefer_alt(int64_t N, int cus, int mt, int alt) {
+    if (alt <= 0 || cus <= 0) return false;
+    auto cost = [&](int m) {
+        const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * m;
+        const int64_t blocks = (N + per_block - 1) / per_block;
+        return ((blocks + cus - 1) / cus) * m;
+    };
+    return cost(alt) < cost(mt);
 }
 
 // One pass over the tiles of one side.  acc_out[t] = 8 * matches (COUNT) or
@@ -454,7 +484,7 @@ hipError_t launch_casc_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* 
                           int64_t cstride, const unsigned long long* src_count, int64_t max_count,
                           int l0, int l1, int u0, int u1, int chunks, int grid_cap,
                           uint32_t* match) {
-    constexpr int MT = sample_tiles<KS, true>();
+    constexpr int MT = casc_sample_tiles<KS>();
     const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
     int64_t bx = (max_count + per_block - 1) / per_block;
     const int64_t cap = grid_cap / chunks > 0 ? grid_cap / chunks : 1;
@@ -470,10 +500,9 @@ hipError_t launch_casc_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* 
     return hipGetLastError();
 }
 
-template <int KS, bool FP4>
-hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
+template <int KS, int MT, bool FP4>
+hipError_t launch_mt(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
                      int mode, uint8_t* flags, uint32_t* match) {
-    constexpr int MT = sample_tiles<KS, FP4>();
     const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
     const dim3 grid(static_cast<unsigned>((N + per_block - 1) / per_block));
     const v4i* lf = reinterpret_cast<const v4i*>(FP4 ? refs->d_lower_frag4 : refs->d_lower_frag);
@@ -491,14 +520,26 @@ hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, i
     return hipGetLastError();
 }
 
+template <int KS, bool FP4>
+hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
+                     int mode, int cus, uint8_t* flags, uint32_t* match) {
+    constexpr int MT = sample_tiles<KS, FP4>();
+    constexpr int ALT = sample_tiles_alt<KS, FP4>();
+    if constexpr (ALT > 0) {
+        if (prefer_alt(N, cus, MT, ALT))
+            return launch_mt<KS, ALT, FP4>(st, refs, xs, N, mode, flags, match);
+    }
+    return launch_mt<KS, MT, FP4>(st, refs, xs, N, mode, flags, match);
+}
+
 }  // namespace
 
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
-                           int mode, bool fp4, uint8_t* flags, uint32_t* match) {
+                           int mode, bool fp4, int cus, uint8_t* flags, uint32_t* match) {
     if (fp4) {
         switch (refs->KS4) {
 #define RSR_KS_CASE(k) \
-    case k: return launch_ks<k, true>(st, refs, xs, N, mode, flags, match);
+    case k: return launch_ks<k, true>(st, refs, xs, N, mode, cus, flags, match);
             RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
             RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
 #undef RSR_KS_CASE
@@ -507,7 +548,7 @@ hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t*
     }
     switch (refs->KS) {
 #define RSR_KS_CASE(k) \
-    case k: return launch_ks<k, false>(st, refs, xs, N, mode, flags, match);
+    case k: return launch_ks<k, false>(st, refs, xs, N, mode, cus, flags, match);
         RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
         RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
         RSR_KS_CASE(11) RSR_KS_CASE(12) RSR_KS_CASE(13) RSR_KS_CASE(14) RSR_KS_CASE(15)

@@ -611,7 +611,8 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
     }
     if (matrix)
         RSR_HIP(ctx, rsr::launch_dom_mfma(ctx->stream, refs, d_samples, N, mode,
-                                          form == RSR_MFMA_FP4, d_flags, match));
+                                          form == RSR_MFMA_FP4, ctx->cu_count, d_flags,
+                                          match));
     else
         RSR_HIP(ctx, rsr::launch_dom_bits(ctx->stream, refs, d_samples, N, mode, d_flags, match));
     return RSR_OK;

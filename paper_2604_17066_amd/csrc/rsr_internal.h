@@ -186,8 +186,10 @@ hipError_t launch_dom_bits(hipStream_t st, const rsr_refs* refs, const uint32_t*
                            int64_t N, int mode, uint8_t* d_flags, uint32_t* d_match);
 hipError_t launch_dom_cascade(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
                               const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap);
+// `cus` (the device's CU count) picks the sample tiles per wave for the grid.
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
-                           int64_t N, int mode, bool fp4, uint8_t* d_flags, uint32_t* d_match);
+                           int64_t N, int mode, bool fp4, int cus, uint8_t* d_flags,
+                           uint32_t* d_match);
 // Split-round test of the cascade in the FP4 matrix-core form (k_dom_mfma.hip).
 hipError_t launch_casc_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* csrc,
                             int64_t cstride, const unsigned long long* src_count, int64_t max_count,

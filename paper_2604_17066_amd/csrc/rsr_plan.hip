@@ -133,7 +133,8 @@ hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice ch
         const rsr_job& jb = p->jobs[j];
         hipError_t e = choice == kMfmaPerJob || choice == kMfma4PerJob
                            ? rsr::launch_dom_mfma(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
-                                                  choice == kMfma4PerJob, jb.d_flags, nullptr)
+                                                  choice == kMfma4PerJob, p->ctx->cu_count,
+                                                  jb.d_flags, nullptr)
                            : rsr::launch_dom_bits(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
                                                   jb.d_flags, nullptr);
         if (e != hipSuccess) return e;

@@ -348,3 +348,48 @@ def test_cascade_fp4_split_rounds_large_rows(rsr_ctx):
     print("rows", refs.R_L, refs.R_U, "unclassified", int((want == 0).sum()))
     np.testing.assert_array_equal(pop, want)
     np.testing.assert_array_equal(auto, want)
+
+
+@pytest.mark.parametrize("form,per_cu", [(R.RSR_MFMA, 640), (R.RSR_MFMA, 512),
+                                         (R.RSR_MFMA_FP4, 1024), (R.RSR_MFMA_FP4, 512)])
+def test_classify_both_sample_tile_counts(rsr_ctx, form, per_cu):
+    """graph2's width (295 bits) builds two sample-tile counts per matrix form
+    (int8: 5 and 4, FP4: 8 and 4) and the launcher picks by N and the CU
+    count; N = per_cu * CUs - 37 selects each of them once (a ragged last
+    block).  Exact counts and labels on sampled indices and the tail."""
+    cfg = WL.configs.graph2()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    N = per_cu * cus - 37
+    m, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, N)
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
+    fc, mt = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, form, want_match=True)
+    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
+    rng = np.random.default_rng(per_cu)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 600), np.arange(N - 300, N)]))
+    x = oracle.sample_at(cfg["p"], cfg["seed"], 0, idx.astype(np.uint64))
+    oc, mL, mU = oracle.classify(cfg["lower"], cfg["upper"], x, mode=1)
+    ol, _, _ = oracle.classify(cfg["lower"], cfg["upper"], x, mode=0)
+    mt = _np(mt).view(np.uint32)
+    np.testing.assert_array_equal(_np(fc)[idx], oc)
+    np.testing.assert_array_equal(mt[idx, 0], mL)
+    np.testing.assert_array_equal(mt[idx, 1], mU)
+    np.testing.assert_array_equal(_np(fl)[idx], ol)
+
+
+@pytest.mark.parametrize("n", [700, 1100, 1250])
+def test_classify_wide_rows(rsr_ctx, n):
+    """Wide rows (int8: 11, 18 and 20 K-steps, FP4: 6, 9 and 10) run with 3, 2
+    and 2 (int8) and 4, 3 and 3 (FP4) sample tiles per wave; N = 3001 spans
+    several blocks and a ragged tail.  Every form against the oracle."""
+    rng = np.random.default_rng(n)
+    p = WL.configs.binary_model(rng.uniform(0.85, 0.995, n))
+    cfg = {"n": n, "K": 2, "p": p, "seed": 21, "stream": 1}
+    # Rows built around some of the samples themselves (a sample's states
+    # raised at random components, or cut down to a few of its surviving
+    # ones), so that lower, upper, both and no matches all occur.
+    x = oracle.sample(p, cfg["seed"], cfg["stream"], 0, 3001)
+    lower = np.maximum(x[rng.integers(0, 3001, 300)], rng.random((300, n)) < 0.6).astype(np.uint8)
+    upper = (x[rng.integers(0, 3001, 280)] & (rng.random((280, n)) < 0.1)).astype(np.uint8)
+    got, want, _ = _classify_both(rsr_ctx, cfg, 3001, lower, upper)
+    _assert_classify(got, want)
+    assert all(int((want[1] == f).sum()) > 0 for f in (0, 1, 2, 3))
