@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz 32-bit vector ops per second.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_BYTES = 8e12
 # MI355X dense int8 matrix-core peak (AMD's published figure, no sparsity).
 MFMA_I8_PEAK_OPS = 5.0e15
 # MI355X dense FP4 (and FP6) matrix-core peak, flops.
@@ -185,6 +186,47 @@ def main():
     step()
     torch.cuda.synchronize()
 
+    # The other stages of the step, each timed alone (HIP events on the context
+    # stream), with the rate their own bound is stated in.
+    def run_sample():
+        ctx.check(lib.rsr_sample(h, model.h, cfg["seed"], 0, 0, N, P(buf.samples)))
+
+    def run_eval():
+        ctx.check(lib.rsr_eval_unknown(h, system.h, P(buf.samples), N, P(buf.flags),
+                                       R.RSR_UNKNOWN_ONLY, P(buf.Y), P(buf.n_eval)))
+
+    def run_grad():
+        ctx.check(lib.rsr_grad(h, model.h, P(buf.samples), P(buf.Y), N, P(buf.G), None))
+
+    def run_estimate():
+        R.rsr_estimate(ctx, buf.flags, buf.Y, N)
+
+    st_reps = max(5, reps)
+    sample_ms = _event_ms(run_sample, st_reps)
+    eval_ms = _event_ms(run_eval, st_reps)
+    grad_ms = _event_ms(run_grad, st_reps)
+    est_ms = _event_ms(run_estimate, st_reps)
+    n_eval = int(buf.n_eval.item())
+    philox_blocks = N * ((n + 3) // 4)   # one block per four components of a sample
+    step_kernels = {
+        # Philox4x32-10: 10 rounds of two 32x32->64-bit products and four XORs
+        # per block of four draws; one compare and one OR per draw and plane.
+        "sample": {"ms": sample_ms, "draws_per_s": N * n / (sample_ms * 1e-3),
+                   "philox_blocks_per_s": philox_blocks / (sample_ms * 1e-3),
+                   "algorithmic_valu_frac": (philox_blocks * 60 + 2 * N * n * (K - 1))
+                   / (sample_ms * 1e-3) / VALU_PEAK_OPS,
+                   "write_GBps": 4.0 * W * N / (sample_ms * 1e-3) / 1e9},
+        "classify_label": {"ms": label_ms},
+        "eval_unknown": {"ms": eval_ms, "evaluated": n_eval,
+                         "phi_evals_per_s": n_eval / (eval_ms * 1e-3)},
+        # Gradient: every sample's packed words once, plus its flag and Y bytes.
+        "grad": {"ms": grad_ms, "read_GBps": (4.0 * W * N + 2.0 * N) / (grad_ms * 1e-3) / 1e9,
+                 "hbm_frac": (4.0 * W * N + 2.0 * N) / (grad_ms * 1e-3) / HBM_PEAK_BYTES},
+        # Estimate: flags and Y once, then fp64 sums on the host-visible counts.
+        "estimate": {"ms": est_ms, "read_GBps": 2.0 * N / (est_ms * 1e-3) / 1e9},
+    }
+    log("stages: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in step_kernels.items()))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, R_L + R_U, args.cpu_seconds)
@@ -232,6 +274,7 @@ def main():
             "kernel_ms": count_ms,
         },
         "classify_forms": kern,
+        "step_kernels": step_kernels,
         "label_classify": {
             "kernel_ms": label_ms,
             "nominal_tests_per_s": tests / (label_ms * 1e-3),

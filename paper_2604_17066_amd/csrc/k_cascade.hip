@@ -35,28 +35,39 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxChunks = 64;
 
-// Reserves output slots for the carrying lanes of the whole block; every
-// thread of the block must call it.  Returns this lane's slot.
-__device__ __forceinline__ int64_t block_reserve(bool carry, unsigned long long* counter,
-                                                 int* s_counts, unsigned long long* s_base) {
+// Reserves output slots for the carrying lanes of the whole block, S samples
+// per lane, with one atomic per block (the reservation counter is shared by
+// the whole grid, so its atomics are the contended part); every thread of the
+// block must call it.  Slots are ordered by (s, wave, lane).  s_counts holds
+// S * kWaves ints.
+template <int S>
+__device__ __forceinline__ void block_reserve(const bool (&carry)[S], unsigned long long* counter,
+                                              int* s_counts, unsigned long long* s_base,
+                                              int64_t (&slot)[S]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t mask = __ballot(carry);
-    if (lane == 0) s_counts[wave] = __popcll(mask);
+    uint64_t mask[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        mask[s] = __ballot(carry[s]);
+        if (lane == 0) s_counts[s * kWaves + wave] = __popcll(mask[s]);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int tot = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            const int c = s_counts[w];
-            s_counts[w] = tot;
+        for (int k = 0; k < S * kWaves; ++k) {
+            const int c = s_counts[k];
+            s_counts[k] = tot;
             tot += c;
         }
         *s_base = tot ? atomicAdd(counter, static_cast<unsigned long long>(tot)) : 0ull;
     }
     __syncthreads();
-    const int64_t slot = static_cast<int64_t>(*s_base) + s_counts[wave] +
-                         __popcll(mask & ((1ull << lane) - 1ull));
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        slot[s] = static_cast<int64_t>(*s_base) + s_counts[s * kWaves + wave] +
+                  __popcll(mask[s] & below);
     __syncthreads();
-    return slot;
 }
 
 // Rows per side staged in LDS at a time (at most 32 KB for both sides).
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
     const uint32_t* __restrict__ up_b, int u0, int u1, uint32_t* __restrict__ dst,
     int32_t* __restrict__ dst_idx, uint32_t* __restrict__ dst_match, int64_t dst_stride,
     unsigned long long* __restrict__ dst_count, int last) {
-    __shared__ int s_counts[kWaves];
+    __shared__ int s_counts[S * kWaves];
     __shared__ unsigned long long s_base;
     __shared__ uint32_t s_rows[2 * tile_rows<W>() * W];
     const int64_t total = src_idx ? static_cast<int64_t>(*src_count) : seg.total;
@@ -182,6 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
 #pragma unroll
         for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
         test_rows<W, S>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
+        bool carry[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const bool hit = mnL[s] == 0u || mnU[s] == 0u;
@@ -192,15 +204,19 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
                 seg_flags(seg, job)[h] =
                     static_cast<uint8_t>(mnL[s] == 0u ? 1 : (mnU[s] == 0u ? 2 : 0));
             }
-            if (last) continue;
-            const bool carry = valid[s] && !hit;
-            const int64_t d = block_reserve(carry, dst_count, s_counts, &s_base);
-            if (carry) {
-                dst_idx[d] = static_cast<int32_t>(gg[s]);
-                dst_match[d] = 0u;
+            carry[s] = valid[s] && !hit;
+        }
+        if (last) continue;
+        int64_t d[S];
+        block_reserve<S>(carry, dst_count, s_counts, &s_base, d);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (carry[s]) {
+                dst_idx[d[s]] = static_cast<int32_t>(gg[s]);
+                dst_match[d[s]] = 0u;
 #pragma unroll
                 for (int w = 0; w < W; ++w)
-                    if (w < w_real) dst[w * dst_stride + d] = x[s][w];
+                    if (w < w_real) dst[w * dst_stride + d[s]] = x[s][w];
             }
         }
     }
@@ -263,9 +279,11 @@ __global__ __launch_bounds__(kBlock) void k_casc_resolve(
             seg_flags(seg, job)[h] = static_cast<uint8_t>((bits & 1u) ? 1 : ((bits & 2u) ? 2 : 0));
         }
         if (last) continue;
-        const bool carry = valid && bits == 0u;
-        const int64_t o = block_reserve(carry, dst_count, s_counts, &s_base);
-        if (carry) {
+        const bool carry[1] = {valid && bits == 0u};
+        int64_t slot[1];
+        block_reserve<1>(carry, dst_count, s_counts, &s_base, slot);
+        const int64_t o = slot[0];
+        if (carry[0]) {
             dst_idx[o] = static_cast<int32_t>(g);
             dst_match[o] = 0u;
             for (int w = 0; w < w_real; ++w) dst[w * dst_stride + o] = csrc[w * cstride + d];
@@ -276,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_resolve(
 template <int W>
 hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
                      const CascadeBuffers& cb, const CascadeShape& shape, int grid_cap) {
-    constexpr int S0 = W <= 16 ? 2 : 1;
+    constexpr int S0 = W <= 12 ? 4 : (W <= 24 ? 2 : 1);
     const int64_t N = seg.total;
     auto blocks_for = [&](int64_t per_block, int64_t cap) {
         int64_t b = (N + per_block - 1) / per_block;

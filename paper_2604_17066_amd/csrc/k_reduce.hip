@@ -10,9 +10,10 @@
 //
 // k_grad_bits: a[j][i] = #{h : Y_h = 1 and x_{h,i} >= j} for every thermometer
 // bit (plane j, component i).  Block column y = packed word w; each thread
-// walks a strided run of samples (about 64) and keeps 32 per-bit counters of
-// its Y-masked words; the block reduces them to one partial row.  Blocks in
-// column 0 also count #{Y = 1}.
+// walks a strided run of samples (about 64), counts the 32 bit positions of
+// its Y-masked words in bit-sliced form and then in 32 plain counters; the
+// block reduces them to one partial row.  Blocks in column 0 also count
+// #{Y = 1}.
 // k_grad_finalize: c[i][s] = a[s][i] - a[s+1][i] (a[0][i] = #{Y = 1},
 // a[K][i] = 0), G[i][s] = (float)c / ((float)N * p[i][s]).
 #include "rsr_internal.h"
@@ -110,9 +111,44 @@ __global__ __launch_bounds__(kBlock) void k_counts_final(const unsigned long lon
     }
 }
 
+// Bit-sliced counters: bit b of s[l] is bit l of this thread's running count
+// of Y-masked words with bit b set, so one added word costs a few bitwise
+// operations for all 32 positions at once (two words enter a full adder at
+// level 0, whose carry ripples up).  With kSliceBits levels a thread counts
+// up to 127 words; words arrive in batches of kBatch (all loads of a batch in
+// flight together), and after kChunkBatches batches (120 words) the slices
+// are added into plain per-bit counters and cleared.
+constexpr int kSliceBits = 7;
+constexpr int kBatch = 8;
+constexpr int kChunkBatches = ((1 << kSliceBits) - 1) / kBatch;
+
+__device__ __forceinline__ void slice_add2(uint32_t (&s)[kSliceBits], uint32_t a, uint32_t b) {
+    const uint32_t t = a ^ b;
+    uint32_t carry = (a & b) | (s[0] & t);
+    s[0] ^= t;
+#pragma unroll
+    for (int l = 1; l < kSliceBits; ++l) {
+        const uint32_t next = s[l] & carry;
+        s[l] ^= carry;
+        carry = next;
+    }
+}
+
+__device__ __forceinline__ void add_batch(uint32_t (&s)[kSliceBits], const uint32_t (&wv)[kBatch],
+                                          const uint8_t (&yv)[kBatch], uint32_t& ny) {
+#pragma unroll
+    for (int q = 0; q < kBatch; q += 2) {
+        const uint32_t ya = yv[q] ? 0xFFFFFFFFu : 0u;
+        const uint32_t yb = yv[q + 1] ? 0xFFFFFFFFu : 0u;
+        ny += (ya & 1u) + (yb & 1u);
+        slice_add2(s, wv[q] & ya, wv[q + 1] & yb);
+    }
+}
+
 // Per-bit masked counts of one packed word column, written as per-block
 // partials: partial[(w * gridDim.x + bx) * 32 + b]; column 0 blocks also write
-// #{Y = 1} to ypart[bx].
+// #{Y = 1} to ypart[bx].  Each thread takes samples h0, h0 + stride, ...
+// (coalesced across the wave).
 __global__ __launch_bounds__(kBlock) void k_grad_bits(const uint32_t* __restrict__ xs,
                                                       const uint8_t* __restrict__ Y, int64_t N,
                                                       uint32_t* __restrict__ partial,
@@ -136,12 +172,44 @@ __global__ __launch_bounds__(kBlock) void k_grad_bits(const uint32_t* __restrict
     uint32_t ny = 0;
     const uint32_t* row = xs + static_cast<int64_t>(w) * N;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t h = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; h < N; h += stride) {
-        const uint32_t y = Y[h] ? 0xFFFFFFFFu : 0u;
-        ny += y & 1u;
-        const uint32_t v = row[h] & y;
+    int64_t h = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    while (h < N) {
+        uint32_t sl[kSliceBits];
 #pragma unroll
-        for (int b = 0; b < 32; ++b) c[b] += (v >> b) & 1u;
+        for (int l = 0; l < kSliceBits; ++l) sl[l] = 0;
+        int k = 0;
+        // Whole batches in range: unconditional loads, all in flight at once.
+        for (; k < kChunkBatches && h + (kBatch - 1) * stride < N; ++k) {
+            uint32_t wv[kBatch];
+            uint8_t yv[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                wv[q] = row[h + q * stride];
+                yv[q] = Y[h + q * stride];
+            }
+            add_batch(sl, wv, yv, ny);
+            h += kBatch * stride;
+        }
+        // The thread's last, partial batch.
+        if (k < kChunkBatches && h < N) {
+            uint32_t wv[kBatch];
+            uint8_t yv[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int64_t hq = h + q * stride;
+                wv[q] = hq < N ? row[hq] : 0u;
+                yv[q] = hq < N ? Y[hq] : 0;
+            }
+            add_batch(sl, wv, yv, ny);
+            h += kBatch * stride;
+        }
+#pragma unroll
+        for (int b = 0; b < 32; ++b) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int l = 0; l < kSliceBits; ++l) v += ((sl[l] >> b) & 1u) << l;
+            c[b] += v;
+        }
     }
     __shared__ uint32_t red[kBlock / 64][33];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

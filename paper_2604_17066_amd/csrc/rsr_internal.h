@@ -173,8 +173,8 @@ struct CascadeBuffers {
 // Rounds of more than split_rows rows (after round 0) are split into
 // rows / split_rows chunks taken by different waves.
 struct CascadeShape {
-    int first = 16;
-    int growth = 4;
+    int first = 32;
+    int growth = 5;
     int split_rows = 128;
     bool mfma_tail = false;  // split rounds in the FP4 matrix-core form (needs refs->KS4 > 0)
 };

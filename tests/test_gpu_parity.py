@@ -393,3 +393,20 @@ def test_classify_wide_rows(rsr_ctx, n):
     got, want, _ = _classify_both(rsr_ctx, cfg, 3001, lower, upper)
     _assert_classify(got, want)
     assert all(int((want[1] == f).sum()) > 0 for f in (0, 1, 2, 3))
+
+
+@pytest.mark.parametrize("n,K,N", [(40, 3, 3_000_001), (33, 2, 17), (70, 4, 65_537)])
+def test_grad_counts_any_run_length(rsr_ctx, n, K, N):
+    """The gradient kernel counts in bit-sliced chunks of 126 samples per
+    thread; at N = 3e6 each thread walks about 180 samples, so the chunk
+    boundary is crossed.  Counts against the oracle on the same samples and a
+    seeded Y with about half ones; tiny and ragged N too."""
+    rng = np.random.default_rng(n * K)
+    p = rng.dirichlet(np.ones(K) * 2.0, size=n)
+    m, xs = _sample(rsr_ctx, p, 99, 4, 0, N)
+    Y = (rng.random(N) < 0.5).astype(np.uint8)
+    G, counts = R.rsr_grad(rsr_ctx, m, xs, torch.from_numpy(Y).to(rsr_ctx.device), N,
+                           want_counts=True)
+    x = oracle.sample(p, 99, 4, 0, N)
+    c, Gref = oracle.grad(p, x, Y)
+    _assert_grad(_np(G), _np(counts), c, Gref)
