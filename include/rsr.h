@@ -178,12 +178,16 @@ rsr_status rsr_system_destroy(rsr_system* sys);
 /* ---- hot path ------------------------------------------------------------ */
 
 /* Draws samples first_sample .. first_sample+N-1 of the model into
- * d_samples (device [W][N] u32, layout above).  The 32-bit uniform word of
- * component i of sample h is word (i mod 4) of Philox4x32-10 (Salmon et al.,
- * SC'11) with counter (i div 4, low32(h), high32(h), stream_id) and key
- * (low32(seed), high32(seed)); the state is then set by the thresholds of
- * rsr_thresholds.  Any sample range can therefore be drawn independently and
- * reproduced on any device or host.  EINVAL: N <= 0, NULL pointer. */
+ * d_samples (device [W][N] u32, layout above).  The 32-bit uniform word u of
+ * component i of sample h is built from Philox4x32-10 (Salmon et al., SC'11)
+ * blocks with key (low32(seed), high32(seed)): its high 16 bits are the half
+ * at position j = i mod 8 (half j mod 2 of word j div 2, low half first) of
+ * the block with counter (i div 8, low32(h), high32(h), stream_id), its low 16
+ * bits the half at the same position of the block with counter
+ * ((i div 8) | 2^31, low32(h), high32(h), stream_id).  The state is
+ * #{s : u >= C[i][s]} with the thresholds of rsr_thresholds.  Any sample range
+ * can therefore be drawn independently and reproduced on any device or host.
+ * EINVAL: N <= 0, NULL pointer. */
 rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint32_t stream_id,
                       uint64_t first_sample, int64_t N, uint32_t* d_samples);
 

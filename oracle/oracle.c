@@ -102,15 +102,27 @@ int or_thresholds(int n, int K, const double* p, uint64_t* C) {
     return 0;
 }
 
-/* The 32-bit word drawn for component i of sample h: word (i mod 4) of
- * Philox4x32-10 with counter (i div 4, low32(h), high32(h), stream_id) and key
- * (low32(seed), high32(seed)). */
+/* 16-bit half at position j (0..7) of a Philox block: half (j mod 2) of word
+ * (j div 2), half 0 being the low 16 bits. */
+static uint32_t block_half(const uint32_t out[4], int j) {
+    return (out[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+}
+
+/* The 32-bit uniform word of component i of sample h.  Its high 16 bits are
+ * the half at position (i mod 8) of the Philox4x32-10 block with counter
+ * (i div 8, low32(h), high32(h), stream_id); its low 16 bits are the half at
+ * the same position of the block whose first counter word also has bit 31
+ * set.  Key (low32(seed), high32(seed)) for both. */
 static uint32_t draw_word(uint64_t seed, uint32_t stream_id, uint64_t h, int i) {
-    uint32_t ctr[4] = {(uint32_t)(i >> 2), (uint32_t)h, (uint32_t)(h >> 32), stream_id};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    uint32_t out[4];
-    or_philox4x32_10(ctr, key, out);
-    return out[i & 3];
+    uint32_t hi_ctr[4] = {(uint32_t)(i >> 3), (uint32_t)h, (uint32_t)(h >> 32), stream_id};
+    uint32_t lo_ctr[4] = {(uint32_t)(i >> 3) | 0x80000000u, (uint32_t)h, (uint32_t)(h >> 32),
+                          stream_id};
+    uint32_t hi[4], lo[4];
+    or_philox4x32_10(hi_ctr, key, hi);
+    or_philox4x32_10(lo_ctr, key, lo);
+    const int j = i & 7;
+    return (block_half(hi, j) << 16) | block_half(lo, j);
 }
 
 static void sample_one(int n, int K, const uint64_t* C, uint64_t seed, uint32_t stream_id,

@@ -1,12 +1,17 @@
-// Monte Carlo sampler: Philox4x32-10 words compared against integer
+// Monte Carlo sampler: 32-bit uniform words compared against integer
 // inverse-CDF thresholds, written straight into the packed thermometer layout
 // (word-major [W][N]; see rsr.h).
 //
-// One thread draws one sample.  A Philox block gives the words of four
-// consecutive components, so a 32-component word of every plane takes eight
-// blocks; the finished words are stored with coalesced 32-bit stores (lanes
-// hold consecutive samples).  The thresholds are identical for every thread,
-// so they are read through the scalar cache.
+// The word of component i is two 16-bit halves at position i mod 8 of two
+// Philox4x32-10 blocks (counter word 0 = i div 8, and the same with bit 31
+// set).  Its high half decides u >= C unless it equals the high half of C,
+// which happens with probability 2^-16 per threshold: only then is the second
+// block drawn.  So one Philox block serves eight components, and the result
+// is exactly that of comparing the full 32-bit word.
+//
+// One thread draws one sample; the finished words are stored with coalesced
+// 32-bit stores (lanes hold consecutive samples).  The thresholds are
+// identical for every thread, so they are read through the scalar cache.
 #include "rsr_internal.h"
 
 namespace rsr {
@@ -35,10 +40,18 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     return {c0, c1, c2, c3};
 }
 
+// Half k (0..7) of a block: half (k mod 2) of word (k div 2), low half first.
+__device__ __forceinline__ uint32_t half16(const Philox4& b, int k) {
+    const uint32_t w = (k >> 1) == 0 ? b.v0 : (k >> 1) == 1 ? b.v1 : (k >> 1) == 2 ? b.v2 : b.v3;
+    return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
 // Draws sample index g (its Philox counter) and stores it as column h of the
-// word-major [W][N] array out.  KM1 = K - 1 thermometer planes.
+// word-major [W][N] array out.  KM1 = K - 1 thermometer planes; thresh and
+// half are the model's two forms of the thresholds (rsr_model).
 template <int KM1>
-__device__ __forceinline__ void draw_sample(const uint64_t* __restrict__ thresh, int n, int PW,
+__device__ __forceinline__ void draw_sample(const uint64_t* __restrict__ thresh,
+                                            const int32_t* __restrict__ half, int n, int PW,
                                             uint32_t key0, uint32_t key1, uint32_t stream_id,
                                             uint64_t g, int64_t h, int64_t N,
                                             uint32_t* __restrict__ out) {
@@ -48,21 +61,36 @@ __device__ __forceinline__ void draw_sample(const uint64_t* __restrict__ thresh,
 #pragma unroll
         for (int s = 0; s < KM1; ++s) acc[s] = 0;
         const int base = wi * 32;
-        const int groups = min(8, (n - base + 3) >> 2);
+        const int groups = min(4, (n - base + 7) >> 3);
         for (int q = 0; q < groups; ++q) {
-            const int i0 = base + q * 4;
-            const Philox4 u = philox4x32_10(static_cast<uint32_t>(i0 >> 2), glo, ghi, stream_id,
-                                            key0, key1);
-            const uint32_t words[4] = {u.v0, u.v1, u.v2, u.v3};
+            const int i0 = base + q * 8;
+            const Philox4 hi = philox4x32_10(static_cast<uint32_t>(i0 >> 3), glo, ghi, stream_id,
+                                             key0, key1);
+            const int32_t* hq = half + static_cast<int64_t>(i0) * KM1 * 2;
+            uint32_t tie = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int i = i0 + k;
-                if (i < n) {
-                    const uint64_t w = words[k];
+            for (int k = 0; k < 8; ++k) {
+                const int32_t u = static_cast<int32_t>(half16(hi, k));
+                int32_t th[2 * KM1];
 #pragma unroll
+                for (int t = 0; t < 2 * KM1; ++t) th[t] = hq[k * KM1 * 2 + t];
+#pragma unroll
+                for (int s = 0; s < KM1; ++s) {
+                    acc[s] |= (u > th[2 * s] ? 1u : 0u) << ((q * 8 + k) & 31);
+                    tie |= u == th[2 * s + 1] ? 1u : 0u;
+                }
+            }
+            if (tie) {
+                // Some threshold shares this lane's high half: its low half,
+                // from the second block, decides.
+                const Philox4 lo = philox4x32_10(static_cast<uint32_t>(i0 >> 3) | 0x80000000u,
+                                                 glo, ghi, stream_id, key0, key1);
+                for (int k = 0; k < 8; ++k) {
+                    const int32_t u = static_cast<int32_t>(half16(hi, k));
                     for (int s = 0; s < KM1; ++s) {
-                        const uint32_t bit = (w >= thresh[i * KM1 + s]) ? 1u : 0u;
-                        acc[s] |= bit << (i & 31);
+                        if (u == hq[(k * KM1 + s) * 2 + 1] &&
+                            half16(lo, k) >= (thresh[(i0 + k) * KM1 + s] & 0xFFFFu))
+                            acc[s] |= 1u << ((q * 8 + k) & 31);
                     }
                 }
             }
@@ -74,14 +102,15 @@ __device__ __forceinline__ void draw_sample(const uint64_t* __restrict__ thresh,
 }
 
 template <int KM1>
-__global__ __launch_bounds__(256) void k_sample(const uint64_t* __restrict__ thresh, int n,
+__global__ __launch_bounds__(256) void k_sample(const uint64_t* __restrict__ thresh,
+                                                const int32_t* __restrict__ half, int n,
                                                 int PW, uint32_t key0, uint32_t key1,
                                                 uint32_t stream_id, uint64_t first, int64_t N,
                                                 uint32_t* __restrict__ out) {
     const int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (h >= N) return;
-    draw_sample<KM1>(thresh, n, PW, key0, key1, stream_id, first + static_cast<uint64_t>(h), h,
-                     N, out);
+    draw_sample<KM1>(thresh, half, n, PW, key0, key1, stream_id,
+                     first + static_cast<uint64_t>(h), h, N, out);
 }
 
 // Every sample of every job of a plan segment (same n and K), grid-stride
@@ -102,7 +131,7 @@ __global__ __launch_bounds__(256) void k_sample_jobs(const JobDev* __restrict__ 
         int64_t h;
         seg_locate(seg, g, j, h);
         const JobDev& jd = jobs[j];
-        draw_sample<KM1>(jd.thresh, n, PW, static_cast<uint32_t>(jd.seed),
+        draw_sample<KM1>(jd.thresh, jd.half, n, PW, static_cast<uint32_t>(jd.seed),
                          static_cast<uint32_t>(jd.seed >> 32), jd.stream_id,
                          static_cast<uint64_t>(h), h, jd.N, jd.samples);
     }
@@ -114,7 +143,7 @@ hipError_t launch_k(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t 
     const int threads = 256;
     const int64_t blocks = (N + threads - 1) / threads;
     hipLaunchKernelGGL(k_sample<KM1>, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, st,
-                       m->d_thresh, m->n, plane_words(m->n), static_cast<uint32_t>(seed),
+                       m->d_thresh, m->d_half, m->n, plane_words(m->n), static_cast<uint32_t>(seed),
                        static_cast<uint32_t>(seed >> 32), stream_id, first, N, d_samples);
     return hipGetLastError();
 }

@@ -252,15 +252,34 @@ rsr_status rsr_model_create(rsr_ctx* ctx, int32_t n, int32_t K, const double* p,
     compute_thresholds(n, K, p, C.data());
     std::vector<float> pf(static_cast<size_t>(n) * K);
     for (size_t i = 0; i < pf.size(); ++i) pf[i] = static_cast<float>(p[i]);
+    const size_t n_pad = (static_cast<size_t>(n) + 7) / 8 * 8;
+    std::vector<int32_t> half(n_pad * (K - 1) * 2);
+    for (size_t i = 0; i < n_pad; ++i)
+        for (int s = 0; s < K - 1; ++s) {
+            int32_t gt = 0x7FFFFFFF, eq = -1;
+            if (i < static_cast<size_t>(n)) {
+                const uint64_t c = C[i * (K - 1) + s];
+                const int32_t ch = static_cast<int32_t>(c >> 16);
+                const bool low_zero = (c & 0xFFFFu) == 0;
+                gt = low_zero ? ch - 1 : ch;
+                eq = low_zero ? -1 : ch;
+            }
+            half[(i * (K - 1) + s) * 2] = gt;
+            half[(i * (K - 1) + s) * 2 + 1] = eq;
+        }
     rsr_model* m = new (std::nothrow) rsr_model();
     if (!m) return fail(ctx, RSR_ENOMEM, "host allocation");
     m->ctx = ctx;
     m->n = n;
     m->K = K;
     hipError_t e = hipMalloc(&m->d_thresh, sizeof(uint64_t) * C.size());
+    if (e == hipSuccess) e = hipMalloc(&m->d_half, sizeof(int32_t) * half.size());
     if (e == hipSuccess) e = hipMalloc(&m->d_p, sizeof(float) * pf.size());
     if (e == hipSuccess)
         e = hipMemcpy(m->d_thresh, C.data(), sizeof(uint64_t) * C.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_half, half.data(), sizeof(int32_t) * half.size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(m->d_p, pf.data(), sizeof(float) * pf.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -275,6 +294,7 @@ rsr_status rsr_model_destroy(rsr_model* m) {
     if (!m) return RSR_EINVAL;
     DeviceGuard g(m->ctx->device);
     if (m->d_thresh) (void)hipFree(m->d_thresh);
+    if (m->d_half) (void)hipFree(m->d_half);
     if (m->d_p) (void)hipFree(m->d_p);
     delete m;
     return RSR_OK;

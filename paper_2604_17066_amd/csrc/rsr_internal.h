@@ -52,6 +52,11 @@ struct rsr_model {
     rsr_ctx* ctx = nullptr;
     int n = 0, K = 0;
     uint64_t* d_thresh = nullptr;  // [n][K-1]
+    // Sampler form of the thresholds, [ceil(n/8)*8][K-1] pairs (gt, eq) of
+    // int32 on the high 16 bits of the uniform word u: u >= C is decided true
+    // by (u >> 16) > gt, and needs the low half only when (u >> 16) == eq.
+    // Padding components never set a bit (gt = INT32_MAX, eq = -1).
+    int32_t* d_half = nullptr;
     float* d_p = nullptr;          // [n][K] fp32 copy of the probabilities
 };
 
@@ -89,6 +94,7 @@ namespace rsr {
 // Device-side record of one job of a batched plan.
 struct JobDev {
     const uint64_t* thresh;  // [n][K-1]
+    const int32_t* half;     // rsr_model::d_half
     const float* p;          // [n][K]
     uint32_t* samples;       // [W][N]
     uint8_t* flags;          // [N]

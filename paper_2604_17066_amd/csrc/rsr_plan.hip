@@ -313,6 +313,7 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
             p->pos[j] = static_cast<int>(host_jobs.size());
             rsr::JobDev d{};
             d.thresh = jb.model->d_thresh;
+            d.half = jb.model->d_half;
             d.p = jb.model->d_p;
             d.samples = jb.d_samples;
             d.flags = jb.d_flags;

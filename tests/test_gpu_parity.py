@@ -55,6 +55,28 @@ def test_sample_bit_identical(rsr_ctx, n, K, N, first, stream):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("kind,n,K,N", [("dirichlet", 64, 16, 200_000), ("uniform", 40, 16, 50_000),
+                                         ("dyadic", 33, 2, 70_001)])
+def test_sample_ties_of_the_high_half(rsr_ctx, kind, n, K, N):
+    """The sampler decides u >= C from the high 16 bits of u unless they equal
+    C's high half (the second Philox block then decides).  With 64 x 15
+    thresholds per sample, 2e5 samples hit that case a few thousand times;
+    uniform K = 16 thresholds (s * 2^28) and dyadic ones (multiples of 2^16)
+    have zero low halves, where the equal high half alone means u >= C."""
+    rng = np.random.default_rng(n + K)
+    if kind == "dirichlet":
+        p = rng.dirichlet(np.ones(K), size=n)
+    elif kind == "uniform":
+        p = np.full((n, K), 1.0 / K)
+    else:
+        q = rng.integers(1, 65536, n) / 65536.0
+        p = np.stack([q, 1.0 - q], axis=1)
+    m, xs = _sample(rsr_ctx, p, 0xC0FFEE, 3, 17, N)
+    got = unpack_states(_np(xs), n, K)
+    want = oracle.sample(p, 0xC0FFEE, 3, 17, N)
+    np.testing.assert_array_equal(got, want)
+
+
 # ------------------------------------------------------------- classifier ----
 
 FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO)

@@ -23,9 +23,13 @@ MUTANTS = {
                                    "const uint32_t mulA = 0xCD9E8D57u, mulB = 0xD2511F53u;"),
     "philox second key not bumped": ("k1 += weyl1;", "k1 += 0u;"),
     "philox output words permuted": ("out[0] = c0; out[1] = c1;", "out[0] = c1; out[1] = c0;"),
-    "counter: component group i/8": ("uint32_t ctr[4] = {(uint32_t)(i >> 2),",
-                                      "uint32_t ctr[4] = {(uint32_t)(i >> 3),"),
-    "draw: wrong word of the block": ("return out[i & 3];", "return out[(i + 1) & 3];"),
+    "counter: component group i/4": ("uint32_t hi_ctr[4] = {(uint32_t)(i >> 3),",
+                                      "uint32_t hi_ctr[4] = {(uint32_t)(i >> 2),"),
+    "draw: wrong half of the block": ("const int j = i & 7;", "const int j = (i + 1) & 7;"),
+    "draw: low half from the high block": ("{(uint32_t)(i >> 3) | 0x80000000u,",
+                                           "{(uint32_t)(i >> 3),"),
+    "draw: halves swapped": ("return (block_half(hi, j) << 16) | block_half(lo, j);",
+                             "return (block_half(lo, j) << 16) | block_half(hi, j);"),
     "threshold: cumulative off by one state": ("acc = acc + p[(size_t)i * K + (s - 1)];",
                                                "acc = acc + p[(size_t)i * K + s];"),
     "state: strict threshold comparison": ("if (u >= C[(size_t)i * (K - 1) + (s - 1)]) state += 1;",

@@ -29,12 +29,17 @@ def test_philox_known_answers():
         assert oracle.philox4x32_10(ctr, key).tolist() == want
 
 
+def _half(block, j):
+    return (int(block[j >> 1]) >> (16 * (j & 1))) & 0xFFFF
+
+
 def test_sample_counter_layout_and_thresholds():
     """With K = 16 uniform states the thresholds are s * 2^28, so the state of
-    component i of sample h is the top nibble of its Philox word: word (i mod 4)
-    of the block with counter (i div 4, low32(h), high32(h), stream) and key
+    component i of sample h is the top nibble of its word, i.e. of the high
+    16-bit half: half (i mod 8) (word (i mod 8) div 2, low half first) of the
+    block with counter (i div 8, low32(h), high32(h), stream) and key
     (low32(seed), high32(seed))."""
-    K, n = 16, 11
+    K, n = 16, 19
     p = np.full((n, K), 1.0 / K)
     seed, stream = 0xDEADBEEF12345678, 9
     first = (1 << 32) - 3
@@ -42,25 +47,43 @@ def test_sample_counter_layout_and_thresholds():
     for hh in range(6):
         h = first + hh
         for i in range(n):
-            ctr = [i >> 2, h & 0xFFFFFFFF, h >> 32, stream]
+            ctr = [i >> 3, h & 0xFFFFFFFF, h >> 32, stream]
             key = [seed & 0xFFFFFFFF, seed >> 32]
-            word = int(oracle.philox4x32_10(ctr, key)[i & 3])
-            assert x[hh, i] == word >> 28
+            assert x[hh, i] == _half(oracle.philox4x32_10(ctr, key), i & 7) >> 12
 
 
 # ------------------------------------------------------------- thresholds ----
 
+def _word_of_sample0_component(i):
+    """The full 32-bit word of component i of sample 0 (seed 0, stream 0):
+    high half from counter (i div 8, 0, 0, 0), low half from the same counter
+    with bit 31 of its first word set."""
+    hi = oracle.philox4x32_10([i >> 3, 0, 0, 0], [0, 0])
+    lo = oracle.philox4x32_10([(i >> 3) | 0x80000000, 0, 0, 0], [0, 0])
+    return (_half(hi, i & 7) << 16) | _half(lo, i & 7)
+
+
 def test_state_flips_exactly_at_the_threshold():
-    """x = 1 iff u >= C: the first word of sample 0 under seed 0, stream 0 is
-    the first Random123 known-answer word 0x6627E8D5; a failure probability
-    of exactly that word / 2^32 puts the threshold on it (state 1), one more
-    unit puts it above (state 0)."""
-    word = 0x6627E8D5
+    """x = 1 iff u >= C.  Component 0 of sample 0 under seed 0, stream 0 has
+    high half 0xE8D5, the low half of the first Random123 known-answer word
+    0x6627E8D5; a failure probability of exactly u / 2^32 puts the threshold
+    on u (state 1), one more unit above it (state 0).  The thresholds share
+    u's high half, so only the low half decides."""
+    word = _word_of_sample0_component(0)
+    assert word >> 16 == 0xE8D5
     for c, want in ((word, 1), (word + 1, 0), (word - 1, 1)):
         q = c / 4294967296.0          # exact in fp64
         p = np.array([[q, 1.0 - q]])
         assert int(oracle.thresholds(p)[0, 0]) == c
         assert int(oracle.sample(p, 0, 0, 0, 1)[0, 0]) == want
+    # The same for a component in the second group of eight, position 5.
+    word = _word_of_sample0_component(13)
+    n = 14
+    for c, want in ((word, 1), (word + 1, 0)):
+        q = c / 4294967296.0
+        p = np.tile([[0.5, 0.5]], (n, 1))
+        p[13] = [q, 1.0 - q]
+        assert int(oracle.sample(p, 0, 0, 0, 1)[0, 13]) == want
 
 
 def test_thresholds_exact_edges():
