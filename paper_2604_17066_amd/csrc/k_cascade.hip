@@ -26,7 +26,7 @@
 // Compaction reserves output slots with one atomic per block (wave ballots,
 // an LDS prefix over the block's waves), not per wave, so the counter is not
 // contended.
-#include "rsr_internal.h"
+#include "compact.h"
 
 namespace rsr {
 namespace {
@@ -34,41 +34,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxChunks = 64;
-
-// Reserves output slots for the carrying lanes of the whole block, S samples
-// per lane, with one atomic per block (the reservation counter is shared by
-// the whole grid, so its atomics are the contended part); every thread of the
-// block must call it.  Slots are ordered by (s, wave, lane).  s_counts holds
-// S * kWaves ints.
-template <int S>
-__device__ __forceinline__ void block_reserve(const bool (&carry)[S], unsigned long long* counter,
-                                              int* s_counts, unsigned long long* s_base,
-                                              int64_t (&slot)[S]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint64_t mask[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        mask[s] = __ballot(carry[s]);
-        if (lane == 0) s_counts[s * kWaves + wave] = __popcll(mask[s]);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int k = 0; k < S * kWaves; ++k) {
-            const int c = s_counts[k];
-            s_counts[k] = tot;
-            tot += c;
-        }
-        *s_base = tot ? atomicAdd(counter, static_cast<unsigned long long>(tot)) : 0ull;
-    }
-    __syncthreads();
-    const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        slot[s] = static_cast<int64_t>(*s_base) + s_counts[s * kWaves + wave] +
-                  __popcll(mask[s] & below);
-    __syncthreads();
-}
 
 // Rows per side staged in LDS at a time (at most 32 KB for both sides).
 template <int W>
@@ -208,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
         }
         if (last) continue;
         int64_t d[S];
-        block_reserve<S>(carry, dst_count, s_counts, &s_base, d);
+        block_reserve<kWaves, S>(carry, dst_count, s_counts, &s_base, d);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (carry[s]) {
@@ -281,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_resolve(
         if (last) continue;
         const bool carry[1] = {valid && bits == 0u};
         int64_t slot[1];
-        block_reserve<1>(carry, dst_count, s_counts, &s_base, slot);
+        block_reserve<kWaves, 1>(carry, dst_count, s_counts, &s_base, slot);
         const int64_t o = slot[0];
         if (carry[0]) {
             dst_idx[o] = static_cast<int32_t>(g);
@@ -323,7 +288,16 @@ hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
         uint32_t* dst_match = cb.match[round & 1];
         unsigned long long* dst_count = reinterpret_cast<unsigned long long*>(cb.counters) + round;
         hipError_t e;
-        if (chunks == 1) {
+        // With the matrix-core tail, an unsplit round after round 0 runs whole
+        // in the FP4 form (test, flags and compaction in one kernel).  Round 0
+        // stays on the vector ALU: most samples stop within its first rows,
+        // which the popcount form's early exit exploits.
+        const bool mfma_round = shape.mfma_tail && refs->KS4 > 0 && round > 0;
+        if (chunks == 1 && mfma_round) {
+            e = launch_casc_mfma_round(st, refs, seg, csrc, cb.stride, src_idx, src_count, N, N,
+                                       l0, l1, u0, u1, grid_cap, dst, dst_idx, dst_match,
+                                       cb.stride, dst_count, last ? 1 : 0);
+        } else if (chunks == 1) {
             if (round == 0)
                 hipLaunchKernelGGL((k_casc_fused<W, S0>), dim3(static_cast<unsigned>(
                                        blocks_for(static_cast<int64_t>(kBlock) * S0, grid_cap))),

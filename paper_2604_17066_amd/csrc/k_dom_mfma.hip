@@ -37,7 +37,7 @@
 // (negative = some row matched) and the block leaves a pass early when every
 // sample is decided (vote once per staged group; lower-flagged samples are
 // decided for the upper pass).
-#include "rsr_internal.h"
+#include "compact.h"
 
 namespace rsr {
 namespace {
@@ -479,6 +479,121 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma(
     }
 }
 
+// A whole round of the LABEL cascade (k_cascade.hip) in the FP4 form when its
+// rows are not split over chunks: the round's samples (the sample array
+// itself in round 0, src_idx null; the compacted undecided samples later)
+// against the tile ranges of both sides, then, in the same block, the flags
+// of the decided samples (of all samples in the last round) and the
+// compaction of the others into dst, with their words, indices and cleared
+// match words.  Tile ranges may reach rows outside the round's rows: on a
+// consistent reference set any match decides the label.
+template <int KS, int MT>
+__global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
+    SegSrc seg, const uint32_t* __restrict__ csrc, int64_t cstride,
+    const int32_t* __restrict__ src_idx, const unsigned long long* __restrict__ src_count,
+    int64_t host_count, int W, const v4i* __restrict__ low_frag, const v4i* __restrict__ low_c,
+    int lt0, int lt1, const v4i* __restrict__ up_frag, const v4i* __restrict__ up_c, int ut0,
+    int ut1, uint32_t* __restrict__ dst, int32_t* __restrict__ dst_idx,
+    uint32_t* __restrict__ dst_match, int64_t dst_stride,
+    unsigned long long* __restrict__ dst_count, int last) {
+    constexpr int kFragV4 = KS * 64;
+    constexpr int kPerBlock = kWaves * 16 * MT;
+    __shared__ v4i lds[2 * tiles_per_stage<KS>() * (KS * 64 + 4)];
+    __shared__ int vote[kWaves];
+    __shared__ uint8_t s_bits[kPerBlock];
+    __shared__ int s_counts[kWaves];
+    __shared__ unsigned long long s_base;
+    const int64_t total = src_count ? static_cast<int64_t>(*src_count) : host_count;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    // Block-uniform loop (the passes and the compaction synchronise the block).
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kPerBlock; b0 < total;
+         b0 += static_cast<int64_t>(gridDim.x) * kPerBlock) {
+        const int64_t wbase = b0 + static_cast<int64_t>(wave) * 16 * MT;
+        v4i bf[MT][KS];
+        bool valid[MT];
+        load_samples<KS, MT, true>(csrc, cstride, total, W, wbase, col, grp, nullptr, bf, valid);
+        int accL[MT], accU[MT];
+        bool none[MT], lowered[MT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            accL[t] = accU[t] = 0;
+            none[t] = false;
+        }
+        mfma_pass<KS, MT, false, true>(bf, low_frag + static_cast<int64_t>(lt0) * kFragV4,
+                                       low_c + static_cast<int64_t>(lt0) * 4, lt1 - lt0, lds, accL,
+                                       none, valid, vote);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            int m = accL[t];
+            m = min(m, __shfl_xor(m, 16));
+            m = min(m, __shfl_xor(m, 32));
+            lowered[t] = m < 0;
+        }
+        mfma_pass<KS, MT, false, true>(bf, up_frag + static_cast<int64_t>(ut0) * kFragV4,
+                                       up_c + static_cast<int64_t>(ut0) * 4, ut1 - ut0, lds, accU,
+                                       lowered, valid, vote);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            int m = accU[t];
+            m = min(m, __shfl_xor(m, 16));
+            m = min(m, __shfl_xor(m, 32));
+            if (grp == 0)
+                s_bits[wave * 16 * MT + 16 * t + col] =
+                    static_cast<uint8_t>((lowered[t] ? 1u : 0u) | (m < 0 ? 2u : 0u));
+        }
+        __syncthreads();
+        // One sample per thread (kPerBlock / kBlock passes, the same for all).
+        for (int j0 = 0; j0 < kPerBlock; j0 += kBlock) {
+            const int j = j0 + static_cast<int>(threadIdx.x);
+            const int64_t d = b0 + j;
+            const bool in = j < kPerBlock && d < total;
+            const uint32_t bits = in ? s_bits[j] : 0u;
+            const int64_t g = in ? (src_idx ? static_cast<int64_t>(src_idx[d]) : d) : 0;
+            if (in && (bits || last)) {
+                int job;
+                int64_t h;
+                seg_locate(seg, g, job, h);
+                seg_flags(seg, job)[h] =
+                    static_cast<uint8_t>((bits & 1u) ? 1 : ((bits & 2u) ? 2 : 0));
+            }
+            if (last) continue;
+            const bool carry[1] = {in && bits == 0u};
+            int64_t slot[1];
+            block_reserve<kWaves, 1>(carry, dst_count, s_counts, &s_base, slot);
+            if (carry[0]) {
+                dst_idx[slot[0]] = static_cast<int32_t>(g);
+                dst_match[slot[0]] = 0u;
+                for (int w = 0; w < W; ++w) dst[w * dst_stride + slot[0]] = csrc[w * cstride + d];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KS>
+hipError_t launch_round_ks(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                           const uint32_t* csrc, int64_t cstride, const int32_t* src_idx,
+                           const unsigned long long* src_count, int64_t host_count,
+                           int64_t max_count, int l0, int l1, int u0, int u1, int grid_cap,
+                           uint32_t* dst, int32_t* dst_idx, uint32_t* dst_match,
+                           int64_t dst_stride, unsigned long long* dst_count, int last) {
+    constexpr int MT = casc_sample_tiles<KS>();
+    const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
+    int64_t bx = (max_count + per_block - 1) / per_block;
+    if (bx > grid_cap) bx = grid_cap;
+    if (bx < 1) bx = 1;
+    hipLaunchKernelGGL((k_casc_mfma_round<KS, MT>), dim3(static_cast<unsigned>(bx)), dim3(kBlock),
+                       0, st, seg, csrc, cstride, src_idx, src_count, host_count, refs->W,
+                       reinterpret_cast<const v4i*>(refs->d_lower_frag4),
+                       reinterpret_cast<const v4i*>(refs->d_lower_cinit4), l0 / 16, (l1 + 15) / 16,
+                       reinterpret_cast<const v4i*>(refs->d_upper_frag4),
+                       reinterpret_cast<const v4i*>(refs->d_upper_cinit4), u0 / 16, (u1 + 15) / 16,
+                       dst, dst_idx, dst_match, dst_stride, dst_count, last);
+    return hipGetLastError();
+}
+
 template <int KS>
 hipError_t launch_casc_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* csrc,
                           int64_t cstride, const unsigned long long* src_count, int64_t max_count,
@@ -553,6 +668,24 @@ hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t*
         RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
         RSR_KS_CASE(11) RSR_KS_CASE(12) RSR_KS_CASE(13) RSR_KS_CASE(14) RSR_KS_CASE(15)
         RSR_KS_CASE(16) RSR_KS_CASE(17) RSR_KS_CASE(18) RSR_KS_CASE(19) RSR_KS_CASE(20)
+#undef RSR_KS_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_casc_mfma_round(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                                  const uint32_t* csrc, int64_t cstride, const int32_t* src_idx,
+                                  const unsigned long long* src_count, int64_t host_count,
+                                  int64_t max_count, int l0, int l1, int u0, int u1, int grid_cap,
+                                  uint32_t* dst, int32_t* dst_idx, uint32_t* dst_match,
+                                  int64_t dst_stride, unsigned long long* dst_count, int last) {
+    switch (refs->KS4) {
+#define RSR_KS_CASE(k) \
+    case k: return launch_round_ks<k>(st, refs, seg, csrc, cstride, src_idx, src_count, host_count, \
+                                      max_count, l0, l1, u0, u1, grid_cap, dst, dst_idx, dst_match, \
+                                      dst_stride, dst_count, last);
+        RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
+        RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
 #undef RSR_KS_CASE
         default: return hipErrorInvalidValue;
     }

@@ -88,6 +88,90 @@ __global__ __launch_bounds__(kBlock) void k_counts(const uint8_t* __restrict__ f
     }
 }
 
+// Counts of flags in the SWAR form: four one-byte flags per 32-bit word (bit 0
+// lower, bit 1 upper), and Y bytes reduced to bit 0 of each byte (nonzero).
+__device__ __forceinline__ void count_word(uint32_t w, uint32_t y, uint32_t (&c)[5]) {
+    const uint32_t lo = w & 0x01010101u, up = (w >> 1) & 0x01010101u;
+    const uint32_t unk = ~(lo | up) & 0x01010101u;
+    const uint32_t ynz = ((((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) >> 7) & 0x01010101u;
+    c[0] += __popc(lo);
+    c[1] += __popc(up & ~lo);
+    c[2] += __popc(unk);
+    c[3] += __popc(lo & up);
+    c[4] += __popc(unk & ynz);
+}
+
+// The counts of k_counts for one job in one launch: 16 flags (and Y bytes)
+// per 16-byte load (both arrays 16-byte aligned), per-block partials, and the
+// last block to finish (a ticket counter, left at zero again) adds them into
+// out[0..4].
+__global__ __launch_bounds__(kBlock) void k_counts_vec(const uint8_t* __restrict__ flags,
+                                                       const uint8_t* __restrict__ Y, int64_t N,
+                                                       unsigned long long* __restrict__ partial,
+                                                       unsigned long long* __restrict__ out,
+                                                       unsigned int* __restrict__ ticket) {
+    uint32_t c[5] = {0, 0, 0, 0, 0};
+    const int64_t chunks = N >> 4;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; k < chunks;
+         k += stride) {
+        const uint4 f = reinterpret_cast<const uint4*>(flags)[k];
+        const uint4 y = Y ? reinterpret_cast<const uint4*>(Y)[k] : make_uint4(0, 0, 0, 0);
+        count_word(f.x, y.x, c);
+        count_word(f.y, y.y, c);
+        count_word(f.z, y.z, c);
+        count_word(f.w, y.w, c);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t h = (chunks << 4) + threadIdx.x; h < N; h += kBlock) {
+            const uint32_t f = flags[h];
+            const uint32_t lo = f & 1u, up = (f >> 1) & 1u, unk = (lo | up) ^ 1u;
+            c[0] += lo;
+            c[1] += up & (lo ^ 1u);
+            c[2] += unk;
+            c[3] += lo & up;
+            c[4] += (unk && Y && Y[h]) ? 1u : 0u;
+        }
+    __shared__ uint32_t red[kBlock / 64][5];
+    __shared__ bool is_last;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const uint32_t v = wave_sum32(c[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long v = 0;
+        for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
+        partial[static_cast<int64_t>(blockIdx.x) * 8 + threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int done = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        is_last = done == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    unsigned long long v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += kBlock)
+        for (int k = 0; k < 5; ++k) v[k] += partial[static_cast<int64_t>(b) * 8 + k];
+    __shared__ unsigned long long red64[kBlock / 64][5];
+    for (int k = 0; k < 5; ++k) {
+        v[k] = wave_sum(v[k]);
+        if (lane == 0) red64[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < kBlock / 64; ++w) sum += red64[w][threadIdx.x];
+        out[threadIdx.x] = sum;
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Sums the per-block partials of k_counts into out[0..4] (one block per job).
 __global__ __launch_bounds__(kBlock) void k_counts_final(const unsigned long long* __restrict__ partial,
                                                          int blocks,
@@ -314,6 +398,18 @@ hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* 
     hipLaunchKernelGGL(k_counts_final, dim3(nj), dim3(kBlock), 0, st,
                        reinterpret_cast<const unsigned long long*>(d_partial),
                        static_cast<int>(blocks), reinterpret_cast<unsigned long long*>(d_counters));
+    return hipGetLastError();
+}
+
+hipError_t launch_counts_vec(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
+                             uint64_t* d_counters, uint64_t* d_partial, uint32_t* d_ticket) {
+    // Four 16-flag chunks per thread: fewer blocks contend for the ticket.
+    int64_t blocks = ((N >> 4) + kBlock * 4 - 1) / (kBlock * 4);
+    if (blocks > kMaxReduceBlocks) blocks = kMaxReduceBlocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_counts_vec, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
+                       d_flags, d_Y, N, reinterpret_cast<unsigned long long*>(d_partial),
+                       reinterpret_cast<unsigned long long*>(d_counters), d_ticket);
     return hipGetLastError();
 }
 

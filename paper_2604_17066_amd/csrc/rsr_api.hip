@@ -214,6 +214,10 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
         hipHostMalloc(reinterpret_cast<void**>(&ctx->ws.host_counts), sizeof(uint64_t) * 16,
                       hipHostMallocDefault) != hipSuccess)
         st = RSR_ENOMEM;
+    // counters[15] is the ticket of the one-launch counts kernel, which
+    // expects it at zero and leaves it there.
+    if (st == RSR_OK && hipMemset(ctx->ws.counters, 0, sizeof(uint64_t) * 16) != hipSuccess)
+        st = RSR_EHIP;
     if (st != RSR_OK) {
         rsr_ctx_destroy(ctx);
         return st;
@@ -619,10 +623,12 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         cb.match[1] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 3 * N);
         cb.stride = N;
         cb.counters = ctx->ws.casc_counters;
-        // The automatic form runs the split rounds in the FP4 matrix-core form
-        // when the handle has its operands; the popcount form stays popcount.
-        rsr::CascadeShape shape;
-        shape.mfma_tail = form == RSR_AUTO && refs->KS4 > 0;
+        // The automatic form runs the rounds after round 0 in the FP4
+        // matrix-core form when the handle has its operands; the popcount
+        // form stays popcount.
+        const rsr::CascadeShape shape = form == RSR_AUTO && refs->KS4 > 0
+                                            ? rsr::mfma_tail_shape()
+                                            : rsr::CascadeShape{};
         RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0));
         RSR_HIP(ctx, rsr::launch_dom_cascade(ctx->stream, refs,
                                              rsr::single_src(d_samples, N, d_flags, nullptr), cb,
@@ -684,8 +690,15 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
     if (!d_flags || !out) return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
     DeviceGuard g(ctx->device);
-    RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
-                                    ctx->ws.count_part));
+    const bool aligned = (reinterpret_cast<uintptr_t>(d_flags) & 15u) == 0 &&
+                         (reinterpret_cast<uintptr_t>(d_Y) & 15u) == 0;
+    if (aligned)
+        RSR_HIP(ctx, rsr::launch_counts_vec(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
+                                            ctx->ws.count_part,
+                                            reinterpret_cast<uint32_t*>(ctx->ws.counters + 15)));
+    else
+        RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
+                                        ctx->ws.count_part));
     RSR_HIP(ctx, hipMemcpyAsync(ctx->ws.host_counts, ctx->ws.counters, sizeof(uint64_t) * 5,
                                 hipMemcpyDeviceToHost, ctx->stream));
     RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));

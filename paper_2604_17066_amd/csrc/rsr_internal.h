@@ -182,8 +182,20 @@ struct CascadeShape {
     int first = 32;
     int growth = 5;
     int split_rows = 128;
-    bool mfma_tail = false;  // split rounds in the FP4 matrix-core form (needs refs->KS4 > 0)
+    // Rounds after round 0 in the FP4 matrix-core form (needs refs->KS4 > 0).
+    bool mfma_tail = false;
 };
+
+// Default shape with the matrix-core tail (measured on graph2: matrix-core
+// rounds favour smaller first rounds, faster growth and larger chunks).
+inline CascadeShape mfma_tail_shape() {
+    CascadeShape s;
+    s.first = 16;
+    s.growth = 6;
+    s.split_rows = 256;
+    s.mfma_tail = true;
+    return s;
+}
 
 // Kernel launchers (each returns the hipError_t of the launch).
 hipError_t launch_sample(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t stream_id,
@@ -196,6 +208,14 @@ hipError_t launch_dom_cascade(hipStream_t st, const rsr_refs* refs, const SegSrc
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* d_samples,
                            int64_t N, int mode, bool fp4, int cus, uint8_t* d_flags,
                            uint32_t* d_match);
+// A whole cascade round (test, flags, compaction) in the FP4 matrix-core form
+// (k_dom_mfma.hip); src_count null means host_count samples.
+hipError_t launch_casc_mfma_round(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                                  const uint32_t* csrc, int64_t cstride, const int32_t* src_idx,
+                                  const unsigned long long* src_count, int64_t host_count,
+                                  int64_t max_count, int l0, int l1, int u0, int u1, int grid_cap,
+                                  uint32_t* dst, int32_t* dst_idx, uint32_t* dst_match,
+                                  int64_t dst_stride, unsigned long long* dst_count, int last);
 // Split-round test of the cascade in the FP4 matrix-core form (k_dom_mfma.hip).
 hipError_t launch_casc_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* csrc,
                             int64_t cstride, const unsigned long long* src_count, int64_t max_count,
@@ -233,6 +253,10 @@ hipError_t launch_boundary(hipStream_t st, const rsr_system* sys, const uint32_t
 hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
                          uint64_t* d_counters, uint64_t* d_partial, const JobDev* jobs = nullptr,
                          int n_jobs = 1);
+// One job's counts in one launch (flags and Y 16-byte aligned); d_ticket is a
+// zero-initialised u32 the kernel leaves at zero.
+hipError_t launch_counts_vec(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
+                             uint64_t* d_counters, uint64_t* d_partial, uint32_t* d_ticket);
 int64_t grad_blocks(int64_t N);
 hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uint32_t* d_samples,
                        const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,

@@ -201,11 +201,7 @@ rsr_status tune_segment(rsr_plan* p, int si) {
     rsr_status st = RSR_OK;
     if (s.refs->consistent) {
         std::vector<Cand> forms = {{kCascade, rsr::CascadeShape{}}};
-        if (s.refs->KS4 > 0) {
-            rsr::CascadeShape tail_shape;
-            tail_shape.mfma_tail = true;
-            forms.push_back({kCascade, tail_shape});
-        }
+        if (s.refs->KS4 > 0) forms.push_back({kCascade, rsr::mfma_tail_shape()});
         st = trial(forms);
         const bool tail = s.shape.mfma_tail;
         std::vector<Cand> shapes;

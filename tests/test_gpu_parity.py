@@ -432,3 +432,25 @@ def test_grad_counts_any_run_length(rsr_ctx, n, K, N):
     x = oracle.sample(p, 99, 4, 0, N)
     c, Gref = oracle.grad(p, x, Y)
     _assert_grad(_np(G), _np(counts), c, Gref)
+
+
+@pytest.mark.parametrize("N,offset,with_Y", [(1_000_003, 0, True), (1_000_003, 1, True),
+                                             (15, 0, True), (16, 0, False), (70_001, 3, False)])
+def test_estimate_counts_any_alignment(rsr_ctx, N, offset, with_Y):
+    """Counts of rsr_estimate: 16-byte aligned flags and Y take the one-launch
+    kernel (16 flags per load, a ragged tail of up to 15), others the
+    per-byte kernels; flags hold every value 0..3 and Y is 0, 1 or larger
+    (counted as 1).  Exact against the oracle, and repeated calls agree."""
+    rng = np.random.default_rng(N + offset)
+    fl = rng.integers(0, 4, N + offset).astype(np.uint8)
+    Y = rng.choice(np.array([0, 1, 2, 255], dtype=np.uint8), N + offset)
+    dev_f = torch.from_numpy(fl).to(rsr_ctx.device)[offset:]
+    dev_Y = torch.from_numpy(Y).to(rsr_ctx.device)[offset:] if with_Y else None
+    want = oracle.counts(fl[offset:], Y[offset:] if with_Y else None)
+    oest = oracle.estimate(want, has_Y=with_Y)
+    for _ in range(3):
+        est = R.rsr_estimate(rsr_ctx, dev_f, dev_Y, N)
+        for k, name in enumerate(oracle.COUNT_NAMES):
+            assert est[name] == int(want[k]), name
+        for k, name in enumerate(oracle.EST_NAMES[:3]):
+            assert est[name] == oest[k], name
