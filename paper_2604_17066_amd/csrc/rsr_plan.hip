@@ -278,6 +278,10 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
             s.K = jb.refs->K;
             s.W = jb.refs->W;
             s.choice = jb.refs->consistent ? kCascade : kBitsPerJob;
+            // Untuned, a cascade takes the matrix-core rounds when the
+            // reference handle has FP4 operands, as rsr_classify's automatic
+            // form does.
+            if (jb.refs->KS4 > 0) s.shape = rsr::mfma_tail_shape();
             p->segs.push_back(s);
             it = p->segs.end() - 1;
         }
