@@ -454,3 +454,26 @@ def test_estimate_counts_any_alignment(rsr_ctx, N, offset, with_Y):
             assert est[name] == int(want[k]), name
         for k, name in enumerate(oracle.EST_NAMES[:3]):
             assert est[name] == oest[k], name
+
+
+@pytest.mark.parametrize("g_idx,level", [(0, 1), (2, 1), (4, 1), (6, 1), (4, 2)])
+def test_eval_all_graph_sizes(rsr_ctx, g_idx, level):
+    """s-t evaluation on graphs of 50 to 360 nodes (one to several node words
+    and edge rounds per lane), every sample evaluated, against the oracle;
+    three-state edges for level 2."""
+    g = WL.configs._batch_graph(g_idx)
+    n = int(g["edge_u"].size)
+    rng = np.random.default_rng(g_idx)
+    K = level + 1
+    p = rng.dirichlet(np.array([1.0, 4.0, 8.0][:K]), size=n) if K == 3 else \
+        WL.configs.binary_model(rng.uniform(0.55, 0.95, n))
+    N = 4099
+    m, xs = _sample(rsr_ctx, p, 13, 2, 0, N)
+    system = R.System(rsr_ctx, g, K=K, level=level)
+    flags = torch.zeros(N, dtype=torch.uint8, device=rsr_ctx.device)
+    Y = R.rsr_eval_unknown(rsr_ctx, system, xs, N, flags, which=R.RSR_ALL)
+    x = oracle.sample(p, 13, 2, 0, N)
+    want, _ = oracle.eval_unknown(g, x, np.zeros(N, dtype=np.uint8), which=1, level=level)
+    got = _np(Y)
+    np.testing.assert_array_equal(got, want)
+    assert 0 < int(want.sum()) < N
