@@ -29,10 +29,18 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
+// Sum over the wave with DPP moves (no LDS round trips): shifts within each
+// row of 16 lanes leave the row's sum in its lane 15, two row broadcasts carry
+// it up, and lane 63 holds the total, which is read into a scalar.  Every
+// lane of the wave must be active.
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xF, 0xF, true));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xF, 0xF, true));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xF, 0xF, true));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xF, 0xF, true));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xA, 0xF, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xC, 0xF, false));
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int64_t count,
@@ -256,7 +264,55 @@ __global__ __launch_bounds__(kBlock) void k_grad_bits(const uint32_t* __restrict
     uint32_t ny = 0;
     const uint32_t* row = xs + static_cast<int64_t>(w) * N;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    int64_t h = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    // Rows 16-byte aligned (N a multiple of 4): four consecutive samples per
+    // 16-byte load and their Y bytes per 32-bit load, four loads of each in
+    // flight per batch.
+    const bool quads = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(xs) & 15u) == 0 &&
+                       (reinterpret_cast<uintptr_t>(Y) & 3u) == 0;
+    if (quads) {
+        constexpr int kQuads = 4;                                // per batch: 16 words
+        constexpr int kChunkQuadBatches = ((1 << kSliceBits) - 1) / (4 * kQuads);
+        const uint4* rowq = reinterpret_cast<const uint4*>(row);
+        const uint32_t* yq = reinterpret_cast<const uint32_t*>(Y);
+        const int64_t NQ = N >> 2;
+        int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+        while (q < NQ) {
+            uint32_t sl[kSliceBits];
+#pragma unroll
+            for (int l = 0; l < kSliceBits; ++l) sl[l] = 0;
+            for (int k = 0; k < kChunkQuadBatches && q < NQ; ++k) {
+                uint4 xv[kQuads];
+                uint32_t yv4[kQuads];
+#pragma unroll
+                for (int i = 0; i < kQuads; ++i) {
+                    const int64_t qi = q + i * stride;
+                    xv[i] = qi < NQ ? rowq[qi] : make_uint4(0, 0, 0, 0);
+                    yv4[i] = qi < NQ ? yq[qi] : 0u;
+                }
+#pragma unroll
+                for (int i = 0; i < kQuads; i += 2) {
+                    const uint32_t wv[kBatch] = {xv[i].x,     xv[i].y,     xv[i].z,     xv[i].w,
+                                                 xv[i + 1].x, xv[i + 1].y, xv[i + 1].z, xv[i + 1].w};
+                    uint8_t yb[kBatch];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        yb[t] = static_cast<uint8_t>(yv4[i] >> (8 * t));
+                        yb[4 + t] = static_cast<uint8_t>(yv4[i + 1] >> (8 * t));
+                    }
+                    add_batch(sl, wv, yb, ny);
+                }
+                q += kQuads * stride;
+            }
+#pragma unroll
+            for (int b = 0; b < 32; ++b) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int l = 0; l < kSliceBits; ++l) v += ((sl[l] >> b) & 1u) << l;
+                c[b] += v;
+            }
+        }
+    }
+    int64_t h = quads ? N : static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     while (h < N) {
         uint32_t sl[kSliceBits];
 #pragma unroll

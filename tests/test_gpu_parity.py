@@ -417,12 +417,14 @@ def test_classify_wide_rows(rsr_ctx, n):
     assert all(int((want[1] == f).sum()) > 0 for f in (0, 1, 2, 3))
 
 
-@pytest.mark.parametrize("n,K,N", [(40, 3, 3_000_001), (33, 2, 17), (70, 4, 65_537)])
+@pytest.mark.parametrize("n,K,N", [(40, 3, 3_000_001), (40, 3, 3_000_000), (33, 2, 17),
+                                   (70, 4, 65_537), (70, 4, 65_536)])
 def test_grad_counts_any_run_length(rsr_ctx, n, K, N):
-    """The gradient kernel counts in bit-sliced chunks of 126 samples per
-    thread; at N = 3e6 each thread walks about 180 samples, so the chunk
-    boundary is crossed.  Counts against the oracle on the same samples and a
-    seeded Y with about half ones; tiny and ragged N too."""
+    """The gradient kernel counts in bit-sliced chunks of at most 120 samples
+    per thread; at N = 3e6 each thread walks about 180 samples, so the chunk
+    boundary is crossed.  N a multiple of 4 takes four samples per load, other
+    N one.  Counts against the oracle on the same samples and a seeded Y with
+    about half ones; tiny and ragged N too."""
     rng = np.random.default_rng(n * K)
     p = rng.dirichlet(np.ones(K) * 2.0, size=n)
     m, xs = _sample(rsr_ctx, p, 99, 4, 0, N)
