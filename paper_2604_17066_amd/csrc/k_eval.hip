@@ -6,12 +6,14 @@
 // for the wave's slots.
 //
 // k_bfs evaluates s-t connectivity at a level on listed samples: one
-// wavefront per sample, the reachable set as a node bitmask in LDS, and
-// edge-parallel sweeps (lane l owns edges l, l+64, ...; an edge is usable when
-// the sample's thermometer plane `level` has its bit set).  A sweep marks both
-// ends of every usable edge with exactly one marked end; the search stops when
-// the sink is marked or a sweep changes nothing.  Each sweep either marks a
-// new node or ends the search, so there are at most n_nodes sweeps.  The grid
+// wavefront per sample, two node bitmasks in LDS grown from the source and
+// from the sink, and edge-parallel sweeps (lane l owns edges l, l+64, ...; an
+// edge is usable when the sample's thermometer plane `level` has its bit
+// set).  A sweep marks, for each set, the other end of every usable edge with
+// exactly one end in it; the search stops when the sets share a node
+// (connected) or one of them stops growing (its component is complete, so
+// they never meet).  Each sweep marks a new node in both sets or ends the
+// search, so there are at most n_nodes sweeps.  The grid
 // is sized on the host without knowing the number of unclassified samples
 // (it lives on the device), and waves stride over the list.
 #include "graph_search.h"
@@ -60,6 +62,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
     const int64_t N = seg.total;
     __shared__ uint32_t s_edges[RSR_MAX_BITS];
     __shared__ uint32_t s_reach[kWavesPerBfsBlock][kMaxNodeWords];
+    __shared__ uint32_t s_reach_t[kWavesPerBfsBlock][kMaxNodeWords];
 
     const int64_t total = which == RSR_ALL ? N : static_cast<int64_t>(*count_ptr);
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_evaluated)
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
     const int node_words = (n_nodes + 31) >> 5;
     const int edge_rounds = (n_edges + 63) >> 6;
     uint32_t* reach = s_reach[wave];
+    uint32_t* reach_t = s_reach_t[wave];
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBfsBlock;
 
     for (int64_t j = first + wave; j < total; j += stride) {
@@ -92,43 +96,62 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs(
                 usable |= static_cast<uint64_t>((word >> (e & 31)) & 1u) << k;
             }
         }
-        for (int wd = lane; wd < node_words; wd += 64) reach[wd] = 0u;
+        for (int wd = lane; wd < node_words; wd += 64) reach[wd] = reach_t[wd] = 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) reach[source >> 5] = 1u << (source & 31);
+        if (lane == 0) {
+            reach[source >> 5] = 1u << (source & 31);
+            reach_t[sink >> 5] |= 1u << (sink & 31);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+        // Two sets grow at once, from the source and from the sink: they
+        // meet iff the sample connects s and t, and one that stops growing is
+        // a whole component (then they never meet).  Growing from both ends
+        // halves the number of sweeps.
         int result = 0;
         while (true) {
-            bool changed = false;
+            bool changed_s = false, changed_t = false;
             uint64_t todo = usable;
             while (todo) {
                 const int k = __ffsll(static_cast<unsigned long long>(todo)) - 1;
                 todo &= todo - 1;
                 const uint32_t uv = s_edges[lane + 64 * k];
                 const uint32_t u = uv & 0xFFFFu, v = uv >> 16;
-                const uint32_t ru = (__hip_atomic_load(&reach[u >> 5], __ATOMIC_RELAXED,
+                const uint32_t su = (__hip_atomic_load(&reach[u >> 5], __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WAVEFRONT) >> (u & 31)) & 1u;
-                const uint32_t rv = (__hip_atomic_load(&reach[v >> 5], __ATOMIC_RELAXED,
+                const uint32_t sv = (__hip_atomic_load(&reach[v >> 5], __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WAVEFRONT) >> (v & 31)) & 1u;
-                if (ru != rv) {
-                    const uint32_t w = ru ? v : u;
+                const uint32_t tu = (__hip_atomic_load(&reach_t[u >> 5], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WAVEFRONT) >> (u & 31)) & 1u;
+                const uint32_t tv = (__hip_atomic_load(&reach_t[v >> 5], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WAVEFRONT) >> (v & 31)) & 1u;
+                if (su != sv) {
+                    const uint32_t w = su ? v : u;
                     atomicOr(&reach[w >> 5], 1u << (w & 31));
-                    changed = true;
+                    changed_s = true;
+                }
+                if (tu != tv) {
+                    const uint32_t w = tu ? v : u;
+                    atomicOr(&reach_t[w >> 5], 1u << (w & 31));
+                    changed_t = true;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            const uint32_t tw = __hip_atomic_load(&reach[sink >> 5], __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
-            const int hit = __builtin_amdgcn_readfirstlane(static_cast<int>((tw >> (sink & 31)) & 1u));
-            if (hit) {
+            bool meet = false;
+            for (int wd = lane; wd < node_words; wd += 64)
+                meet = meet || (__hip_atomic_load(&reach[wd], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WAVEFRONT) &
+                                __hip_atomic_load(&reach_t[wd], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WAVEFRONT)) != 0u;
+            if (__any(meet)) {
                 result = 1;
                 break;
             }
-            if (!__any(changed)) break;
+            if (!__any(changed_s) || !__any(changed_t)) break;
         }
         if (lane == 0) seg_Y(seg, job)[h] = static_cast<uint8_t>(result);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
