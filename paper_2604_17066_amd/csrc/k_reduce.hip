@@ -153,6 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_counts_vec(const uint8_t* __restrict
         unsigned long long v = 0;
         for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
         partial[static_cast<int64_t>(blockIdx.x) * 8 + threadIdx.x] = v;
+        // The writer itself makes its partial visible device-wide before the
+        // ticket is taken.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();
     if (threadIdx.x == 0) {
