@@ -18,14 +18,16 @@
 //     into the sample's match word, and k_casc_resolve then writes flags and
 //     compacts the still undecided samples.  A round whose rows do not warrant
 //     a split runs k_casc_fused on the compact buffer instead.  With
-//     shape.mfma_tail the split rounds' tests run in the FP4 matrix-core form
-//     (k_casc_mfma of k_dom_mfma.hip), which makes more tests per second once
-//     the undecided samples have to be tested against many rows.
+//     shape.mfma_tail every round after round 0 runs in the FP4 matrix-core
+//     form (k_dom_mfma.hip), which makes more tests per second once the
+//     undecided samples have to be tested against many rows: an unsplit
+//     round is one k_casc_mfma_round (test, flags and compaction), a split
+//     round k_casc_mfma per chunk and then k_casc_resolve.
 //   the last round flags every remaining sample as unclassified.
 //
-// Compaction reserves output slots with one atomic per block (wave ballots,
-// an LDS prefix over the block's waves), not per wave, so the counter is not
-// contended.
+// Compaction reserves output slots with one atomic per block for all of the
+// block's samples (wave ballots, an LDS prefix over the block's waves;
+// compact.h): the grid-wide counter's atomics are the contended part.
 #include "compact.h"
 
 namespace rsr {
