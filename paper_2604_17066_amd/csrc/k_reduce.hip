@@ -1,12 +1,13 @@
 // Reductions: estimator counts (section 3.3.1) and the score-function
 // gradient counts.
 //
-// Both reductions are two-pass and atomic-free: blocks write partial sums to a
-// workspace and a second kernel adds them in a fixed order, so results do not
-// depend on scheduling and no address is contended.
+// Blocks write partial sums to a workspace, which are added in a fixed order
+// (integers: the results do not depend on scheduling either way).
 //
 // k_counts: one pass over flags (and Y) with per-thread counters, wavefront
 // and block reductions, one partial row per block; k_counts_final adds rows.
+// k_counts_vec: the same for one job in one launch, 16 flags per load; the
+// last block to finish (one ticket atomic per block) adds the rows.
 //
 // k_grad_bits: a[j][i] = #{h : Y_h = 1 and x_{h,i} >= j} for every thermometer
 // bit (plane j, component i).  Block column y = packed word w; each thread
