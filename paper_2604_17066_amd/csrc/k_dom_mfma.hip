@@ -238,11 +238,16 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
 #pragma unroll
             for (int s = 0; s < KS; ++s) a[s] = tile[s * 64 + lane];
             v4i acc[MT];
+            // The two waves of a SIMD alternate between products and folds:
+            // a wave issuing products goes first, so the matrix core is fed
+            // while the other wave folds.
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < KS; ++s)
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
                     acc[t] = mfma_step<FP4>(a[s], bf[t][s], s == 0 ? c0 : acc[t]);
+            __builtin_amdgcn_s_setprio(0);
             fold<MT, COUNT, FP4>(prev, acc_out);
 #pragma unroll
             for (int t = 0; t < MT; ++t) prev[t] = acc[t];
