@@ -168,7 +168,7 @@ inline bool prefer_alt(int64_t N, int cus, int mt, int alt) {
 // accumulator starts, so the loop has no global load on its critical path;
 // tiles past the end are staged as zeros (never a match), so every group
 // runs all of its tiles without a branch.
-template <int KS, int MT, bool COUNT, bool FP4>
+template <int KS, int MT, bool COUNT, bool FP4, bool PRIO = (KS * MT < 30)>
 __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
                                           const v4i* __restrict__ cinit, int tiles,
                                           v4i* __restrict__ lds, int (&acc_out)[MT],
@@ -240,14 +240,18 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
             v4i acc[MT];
             // The two waves of a SIMD alternate between products and folds:
             // a wave issuing products goes first, so the matrix core is fed
-            // while the other wave folds.
-            __builtin_amdgcn_s_setprio(1);
+            // while the other wave folds.  The priority changes keep the
+            // products together, which needs more registers; PRIO is off
+            // where that would spill (from KS * MT = 30 on, and in the
+            // cascade kernels beyond KS = 3).
+            constexpr bool kPrio = PRIO;
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < KS; ++s)
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
                     acc[t] = mfma_step<FP4>(a[s], bf[t][s], s == 0 ? c0 : acc[t]);
-            __builtin_amdgcn_s_setprio(0);
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
             fold<MT, COUNT, FP4>(prev, acc_out);
 #pragma unroll
             for (int t = 0; t < MT; ++t) prev[t] = acc[t];
@@ -459,9 +463,10 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma(
             accL[t] = accU[t] = 0;
             none[t] = false;
         }
-        mfma_pass<KS, MT, false, true>(bf, low_frag + static_cast<int64_t>(cl0) * kFragV4,
-                                       low_c + static_cast<int64_t>(cl0) * 4, cl1 - cl0, lds, accL,
-                                       none, valid, vote);
+        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+            bf, low_frag + static_cast<int64_t>(cl0) * kFragV4,
+            low_c + static_cast<int64_t>(cl0) * 4, cl1 - cl0, lds, accL,
+            none, valid, vote);
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
             int m = accL[t];
@@ -469,9 +474,10 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma(
             m = min(m, __shfl_xor(m, 32));
             lowered[t] = m < 0;
         }
-        mfma_pass<KS, MT, false, true>(bf, up_frag + static_cast<int64_t>(cu0) * kFragV4,
-                                       up_c + static_cast<int64_t>(cu0) * 4, cu1 - cu0, lds, accU,
-                                       lowered, valid, vote);
+        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+            bf, up_frag + static_cast<int64_t>(cu0) * kFragV4,
+            up_c + static_cast<int64_t>(cu0) * 4, cu1 - cu0, lds, accU,
+            lowered, valid, vote);
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
             int m = accU[t];
@@ -526,9 +532,10 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
             accL[t] = accU[t] = 0;
             none[t] = false;
         }
-        mfma_pass<KS, MT, false, true>(bf, low_frag + static_cast<int64_t>(lt0) * kFragV4,
-                                       low_c + static_cast<int64_t>(lt0) * 4, lt1 - lt0, lds, accL,
-                                       none, valid, vote);
+        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+            bf, low_frag + static_cast<int64_t>(lt0) * kFragV4,
+            low_c + static_cast<int64_t>(lt0) * 4, lt1 - lt0, lds, accL,
+            none, valid, vote);
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
             int m = accL[t];
@@ -536,9 +543,10 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
             m = min(m, __shfl_xor(m, 32));
             lowered[t] = m < 0;
         }
-        mfma_pass<KS, MT, false, true>(bf, up_frag + static_cast<int64_t>(ut0) * kFragV4,
-                                       up_c + static_cast<int64_t>(ut0) * 4, ut1 - ut0, lds, accU,
-                                       lowered, valid, vote);
+        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+            bf, up_frag + static_cast<int64_t>(ut0) * kFragV4,
+            up_c + static_cast<int64_t>(ut0) * 4, ut1 - ut0, lds, accU,
+            lowered, valid, vote);
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
             int m = accU[t];
