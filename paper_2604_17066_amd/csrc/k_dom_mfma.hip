@@ -110,10 +110,18 @@ __device__ __forceinline__ void fold(const v4i (&r)[MT], int (&acc_out)[MT]) {
 // SIMD), so the barrier at the end of a group idles the whole CU; large groups
 // make that rare and give the global loads of the next group a whole group of
 // matrix work to land.  The double-buffered stage takes 2 * TPS * (KS KB +
-// 64 B) of LDS, at most 83 KB.
+// 64 B) of LDS, at most 83 KB (75 KB at KS = 3, where twelve tiles measure
+// faster than eight).
 template <int KS>
 constexpr int tiles_per_stage() {
-    return KS <= 5 ? 8 : (KS <= 10 ? 4 : 2);
+    return KS == 3 ? 12 : KS <= 5 ? 8 : (KS <= 10 ? 4 : 2);
+}
+
+// Reference tiles per stage of the cascade's FP4 kernels: eight at KS = 3
+// (their short row ranges gain nothing from twelve), else as above.
+template <int KS>
+constexpr int casc_tiles_per_stage() {
+    return KS == 3 ? 8 : tiles_per_stage<KS>();
 }
 
 // Sample tiles per wave: B fragments take MT * KS * 4 VGPRs, and with the two
@@ -168,7 +176,8 @@ inline bool prefer_alt(int64_t N, int cus, int mt, int alt) {
 // accumulator starts, so the loop has no global load on its critical path;
 // tiles past the end are staged as zeros (never a match), so every group
 // runs all of its tiles without a branch.
-template <int KS, int MT, bool COUNT, bool FP4, bool PRIO = (KS * MT < 30)>
+template <int KS, int MT, bool COUNT, bool FP4, bool PRIO = (KS * MT < 30),
+          int TPS = tiles_per_stage<KS>()>
 __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
                                           const v4i* __restrict__ cinit, int tiles,
                                           v4i* __restrict__ lds, int (&acc_out)[MT],
@@ -176,7 +185,6 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
                                           int* vote) {
     constexpr int kFragV4 = KS * 64;      // operand v4i per reference tile
     constexpr int kTileV4 = kFragV4 + 4;  // plus 16 accumulator starts
-    constexpr int TPS = tiles_per_stage<KS>();
     constexpr int kStageV4 = TPS * kTileV4;
     constexpr int kPerThread = (kStageV4 + kBlock - 1) / kBlock;
     const int lane = threadIdx.x & 63;
@@ -435,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma(
     const unsigned long long* __restrict__ src_count, int W, const v4i* __restrict__ low_frag,
     const v4i* __restrict__ low_c, int lt0, int lt1, const v4i* __restrict__ up_frag,
     const v4i* __restrict__ up_c, int ut0, int ut1, uint32_t* __restrict__ match) {
-    __shared__ v4i lds[2 * tiles_per_stage<KS>() * (KS * 64 + 4)];
+    __shared__ v4i lds[2 * casc_tiles_per_stage<KS>() * (KS * 64 + 4)];
     __shared__ int vote[kWaves];
     const int64_t total = static_cast<int64_t>(*src_count);
     const int lane = threadIdx.x & 63;
@@ -463,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma(
             accL[t] = accU[t] = 0;
             none[t] = false;
         }
-        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+        mfma_pass<KS, MT, false, true, (KS <= 3), casc_tiles_per_stage<KS>()>(
             bf, low_frag + static_cast<int64_t>(cl0) * kFragV4,
             low_c + static_cast<int64_t>(cl0) * 4, cl1 - cl0, lds, accL,
             none, valid, vote);
@@ -474,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma(
             m = min(m, __shfl_xor(m, 32));
             lowered[t] = m < 0;
         }
-        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+        mfma_pass<KS, MT, false, true, (KS <= 3), casc_tiles_per_stage<KS>()>(
             bf, up_frag + static_cast<int64_t>(cu0) * kFragV4,
             up_c + static_cast<int64_t>(cu0) * 4, cu1 - cu0, lds, accU,
             lowered, valid, vote);
@@ -509,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
     unsigned long long* __restrict__ dst_count, int last) {
     constexpr int kFragV4 = KS * 64;
     constexpr int kPerBlock = kWaves * 16 * MT;
-    __shared__ v4i lds[2 * tiles_per_stage<KS>() * (KS * 64 + 4)];
+    __shared__ v4i lds[2 * casc_tiles_per_stage<KS>() * (KS * 64 + 4)];
     __shared__ int vote[kWaves];
     __shared__ uint8_t s_bits[kPerBlock];
     __shared__ int s_counts[kWaves];
@@ -532,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
             accL[t] = accU[t] = 0;
             none[t] = false;
         }
-        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+        mfma_pass<KS, MT, false, true, (KS <= 3), casc_tiles_per_stage<KS>()>(
             bf, low_frag + static_cast<int64_t>(lt0) * kFragV4,
             low_c + static_cast<int64_t>(lt0) * 4, lt1 - lt0, lds, accL,
             none, valid, vote);
@@ -543,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
             m = min(m, __shfl_xor(m, 32));
             lowered[t] = m < 0;
         }
-        mfma_pass<KS, MT, false, true, (KS <= 3)>(
+        mfma_pass<KS, MT, false, true, (KS <= 3), casc_tiles_per_stage<KS>()>(
             bf, up_frag + static_cast<int64_t>(ut0) * kFragV4,
             up_c + static_cast<int64_t>(ut0) * 4, ut1 - ut0, lds, accU,
             lowered, valid, vote);
