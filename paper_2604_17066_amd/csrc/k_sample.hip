@@ -28,8 +28,9 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     for (int round = 0; round < 10; ++round) {
         const uint64_t a = static_cast<uint64_t>(0xD2511F53u) * c0;
         const uint64_t b = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        const uint32_t y0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
-        const uint32_t y2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        // Three-input XORs as one v_bitop3_b32 each (truth table 0x96).
+        const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(b >> 32), c1, k0, 0x96);
+        const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(a >> 32), c3, k1, 0x96);
         c1 = static_cast<uint32_t>(b);
         c3 = static_cast<uint32_t>(a);
         c0 = y0;
