@@ -219,9 +219,10 @@ constexpr int kBatch = 8;
 constexpr int kChunkBatches = ((1 << kSliceBits) - 1) / kBatch;
 
 __device__ __forceinline__ void slice_add2(uint32_t (&s)[kSliceBits], uint32_t a, uint32_t b) {
-    const uint32_t t = a ^ b;
-    uint32_t carry = (a & b) | (s[0] & t);
-    s[0] ^= t;
+    // Full adder at level 0 as two v_bitop3_b32: sum = a ^ b ^ s0 (truth
+    // table 0x96), carry = majority(a, b, s0) (0xE8).
+    uint32_t carry = __builtin_amdgcn_bitop3_b32(a, b, s[0], 0xE8);
+    s[0] = __builtin_amdgcn_bitop3_b32(a, b, s[0], 0x96);
 #pragma unroll
     for (int l = 1; l < kSliceBits; ++l) {
         const uint32_t next = s[l] & carry;
