@@ -218,13 +218,13 @@ def main():
     n_eval = int(buf.n_eval.item())
     philox_blocks = N * ((n + 7) // 8)   # one block per eight components of a sample
     step_kernels = {
-        # Philox4x32-10: 10 rounds of two 32x32->64-bit products and four XORs
-        # per block of eight 16-bit halves (the second block, drawn with
-        # probability 2^-16 per threshold, is left out); a compare, a bit
-        # insert and a tie test per draw and plane.
+        # Philox4x32-10: 10 rounds of two 32x32->64-bit products and two
+        # three-input XORs per block of eight 16-bit halves (the second block,
+        # drawn with probability 2^-16 per threshold, is left out); a compare,
+        # a bit insert and a tie test per draw and plane.
         "sample": {"ms": sample_ms, "draws_per_s": N * n / (sample_ms * 1e-3),
                    "philox_blocks_per_s": philox_blocks / (sample_ms * 1e-3),
-                   "algorithmic_valu_frac": (philox_blocks * 60 + 3 * N * n * (K - 1))
+                   "algorithmic_valu_frac": (philox_blocks * 40 + 3 * N * n * (K - 1))
                    / (sample_ms * 1e-3) / VALU_PEAK_OPS,
                    "write_GBps": 4.0 * W * N / (sample_ms * 1e-3) / 1e9},
         "classify_label": {"ms": label_ms},

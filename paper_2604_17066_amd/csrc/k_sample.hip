@@ -63,7 +63,11 @@ __device__ __forceinline__ void draw_sample(const uint64_t* __restrict__ thresh,
         for (int s = 0; s < KM1; ++s) acc[s] = 0;
         const int base = wi * 32;
         const int groups = min(4, (n - base + 7) >> 3);
-        for (int q = 0; q < groups; ++q) {
+        // Unrolled over the word's four groups, so every bit position below
+        // is a constant.
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= groups) break;
             const int i0 = base + q * 8;
             const Philox4 hi = philox4x32_10(static_cast<uint32_t>(i0 >> 3), glo, ghi, stream_id,
                                              key0, key1);
