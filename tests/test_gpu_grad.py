@@ -1,12 +1,12 @@
 """GPU tests of the score-function gradient through the autograd wrapper:
 
 * exact importances on the tiny graph (brute force over 2^20 states): every
-  dP/dp_i within 4 standard errors, and the z-scores calibrated (mean z^2
+  dP/dp_i within 3 standard errors, and the z-scores calibrated (mean z^2
   near 1);
 * common-random-number central differences: P is multilinear in each p_i,
   so (P(p_i + d) - P(p_i - d)) / 2d is an unbiased estimate of dP/dp_i with
   no truncation error; it must agree with the score-function value within
-  4 combined standard errors.
+  3 combined standard errors.
 (The fp32 gradient's 1e-5 relative agreement with the fp64 oracle is tested
 in test_gpu_parity.py.)"""
 import math
@@ -55,8 +55,8 @@ def test_importance_against_exact_tiny(rsr_ctx):
     z = (grad - I_exact) / se
     print("max |z| =", np.abs(z).max(), "mean z^2 =", np.mean(z * z))
     assert float(P) == est["P"]
-    assert abs(float(P) - P_exact) <= 4 * est["se"]
-    assert np.all(np.abs(z) <= 4.0)
+    assert abs(float(P) - P_exact) <= 3 * est["se"]
+    assert np.all(np.abs(z) <= 3.0)
     assert 0.2 <= np.mean(z * z) <= 3.0
 
 
@@ -92,6 +92,6 @@ def test_importance_against_crn_differences(rsr_ctx):
         assert d.min() >= 0      # common random numbers: raising p_i never lowers Y
         fd = d.mean() / span
         se_fd = math.sqrt(d.mean() * (1 - d.mean()) / N) / span
-        tol = 4.0 * math.hypot(se_fd, se_sf[i])
+        tol = 3.0 * math.hypot(se_fd, se_sf[i])
         print(f"i={i}: score-function {grad[i]:.5f}, CRN difference {fd:.5f}, tol {tol:.5f}")
         assert abs(fd - grad[i]) <= tol
