@@ -428,7 +428,7 @@ def stage1_leg(ctx, with_cpu):
 
 
 def global_leg(ctx):
-    """Global connectivity (sections 4.3-4.4) on graph2 (119 nodes / 295
+    """Global connectivity (sections 4.2 and 4.5) on graph2 (119 nodes / 295
     edges): Stage 1 from empty reference sets (1e5 samples and 8192 searches
     per iteration, until 1e5 rows or p_u < 1e-5), then Stage 2 with those rows
     on 1e6 samples, for the connected level; and the boundary-search rate of

@@ -30,6 +30,8 @@
  *   validated before any launch; asynchronous device faults surface as
  *   RSR_EHIP at the next synchronising call.
  * - A context is not thread-safe; use one per host thread.
+ * - Handles (models, reference sets, systems, plans) belong to the context
+ *   that created them and must be destroyed before it.
  *
  * State encoding (the layout of d_samples)
  * ----------------------------------------
@@ -65,7 +67,8 @@ typedef enum {
 enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
 enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2, RSR_MFMA_FP4 = 3 };  /* rsr_classify form */
 enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown which */
-enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2, RSR_SYS_MAX_FLOW = 3 };  /* rsr_system_desc kind */
+enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2, RSR_SYS_MAX_FLOW = 3,
+       RSR_SYS_HOST_CALLBACK = 4 };  /* rsr_system_desc kind */
 
 /* Limits of this build. */
 #define RSR_MAX_K 16
@@ -90,8 +93,9 @@ typedef struct {
     double p_L, p_U, p_u, P, se, cov;
 } rsr_estimate_t;
 
-/* System function description (section 2.1): components are the undirected
- * edges (edge_u[e], edge_v[e]) of a graph with n_nodes nodes; n_edges = n.
+/* System function description (section 2.1).  Graph systems: components are
+ * the undirected edges (edge_u[e], edge_v[e]) of a graph with n_nodes nodes;
+ * n_edges = n.
  *   RSR_SYS_ST_CONNECTIVITY: Phi = 1 when sink is reachable from source over
  *     edges whose state is at least `level` (1 <= level <= K-1), else 0:
  *     single-OD connectivity for K = 2, and the level-`level` bottleneck
@@ -101,20 +105,31 @@ typedef struct {
  *     the working edges connect every node but some single edge failure
  *     would disconnect them, 2 when every pair of nodes keeps two
  *     edge-disjoint paths (no bridge); Phi = 1 when that state is at least
- *     `level` (1 or 2) (sections 4.3 and 4.4).  source and sink are unused.
+ *     `level` (1 or 2) (sections 4.2 and 4.5).  source and sink are unused.
  *   RSR_SYS_MAX_FLOW: edge e carries up to x_e units of flow in either
  *     direction; the system state is the maximum flow from source to sink,
  *     and Phi = 1 when it is at least `level` (the demand d >= 1).  Its
- *     reference states are the d-minimal path and cut vectors (section 2.2). */
+ *     reference states are the d-minimal path and cut vectors (section 2.2).
+ * Any other coherent system function (section 2.1 only asks that Phi be
+ * non-decreasing in every component state):
+ *   RSR_SYS_HOST_CALLBACK: phi(x, n, user) is called on the host with a state
+ *     vector x (n bytes, states 0..K-1, valid only during the call) and
+ *     returns the system state S >= 0; Phi = 1 when S >= `level` (>= 1).
+ *     n_edges = n; the graph fields are unused and may be 0 / NULL.  phi is
+ *     called from the thread that calls the library, one state at a time,
+ *     and must not call the library.  A negative return aborts the call that
+ *     made it with RSR_EINVAL. */
 typedef struct {
-    int32_t kind;       /* RSR_SYS_ST_CONNECTIVITY, _GLOBAL_CONNECTIVITY or _MAX_FLOW */
-    int32_t n_nodes;    /* 2..RSR_MAX_NODES */
+    int32_t kind;       /* one of the RSR_SYS_* kinds */
+    int32_t n_nodes;    /* graph systems: 2..RSR_MAX_NODES */
     int32_t n_edges;    /* = n, the number of components */
     int32_t K;          /* states per component */
     const int32_t* edge_u;  /* host [n_edges], node ids in [0, n_nodes) */
     const int32_t* edge_v;  /* host [n_edges] */
-    int32_t source, sink;   /* distinct node ids (unused for global connectivity) */
+    int32_t source, sink;   /* distinct node ids (s-t connectivity and max flow) */
     int32_t level;
+    int32_t (*phi)(const uint8_t* x, int32_t n, void* user);  /* RSR_SYS_HOST_CALLBACK */
+    void* user;             /* passed to phi unchanged */
 } rsr_system_desc;
 
 /* ---- context ------------------------------------------------------------ */
@@ -147,6 +162,14 @@ rsr_status rsr_thresholds(int32_t n, int32_t K, const double* p, uint64_t* C);
 rsr_status rsr_model_create(rsr_ctx* ctx, int32_t n, int32_t K, const double* p,
                             rsr_model** out);
 rsr_status rsr_model_destroy(rsr_model* model);
+/* Replaces the probabilities of a model (same n and K) without allocating:
+ * validates p as rsr_model_create does, then uploads the new thresholds and
+ * probabilities through the model's pinned staging buffer on the context
+ * stream.  Asynchronous: work enqueued on the stream before the call sees
+ * the old values, work enqueued after it the new ones.  If the previous
+ * upload has not yet left the staging buffer, the call first waits for it.
+ * EINVAL as for rsr_model_create (the model is then unchanged). */
+rsr_status rsr_model_update(rsr_model* model, const double* p);
 
 /* Reference states for one target level (section 2.2, sets L(m') and U(m')):
  * lower = host [R_L][n] uint8 states, each certifying S < level for every
@@ -238,6 +261,16 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
 rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
                     const uint8_t* d_Y, int64_t N, float* d_G, uint64_t* d_counts);
 
+/* Binary Birnbaum importance (K = 2 with p[i][1] the survival probability of
+ * component i and p[i][0] = 1 - p[i][1]): the derivative of P along that
+ * constraint, I_i = dP/dp[i][1] - dP/dp[i][0] = c[i][1] / (N p[i][1]) -
+ * c[i][0] / (N p[i][0]), with the counts c of rsr_grad, each quotient formed
+ * in fp64 from the model's fp64 probabilities (0 where p = 0) and the
+ * difference rounded once to fp32.  d_I is device [n] f32.  EINVAL: K != 2,
+ * NULL argument, N <= 0. */
+rsr_status rsr_importance(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
+                          const uint8_t* d_Y, int64_t N, float* d_I);
+
 /* ---- Stage 1: new reference states -------------------------------------- */
 
 /* Componentwise boundary search (section 3.4, fig. x1x2_find_ref) from the
@@ -323,13 +356,28 @@ typedef struct {
     float* d_G;
 } rsr_job;
 
-/* Builds a plan for n_jobs jobs: chooses a kernel configuration per job shape
- * (timing candidates once per distinct shape unless `tune` is 0), orders the
- * work, and records every launch of every job into one HIP graph.  The plan
- * keeps the job array's pointers, so the handles and buffers must outlive it.
- * Synchronous. */
-rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, int32_t tune,
-                           rsr_plan** out);
+/* Builds a plan for n_jobs jobs: chooses a kernel configuration per job shape,
+ * orders the work, and records every launch of every job into one HIP graph.
+ * The configuration of a segment (the jobs sharing a reference set and a
+ * system) is chosen by timing candidates on its own samples, with results
+ * kept in a tuning cache:
+ *   tune_cache NULL:  no timing; every segment takes the default
+ *                     configuration (the automatic classification form);
+ *   tune_cache "":    every segment is timed, nothing is stored;
+ *   a file path:      a JSON object whose keys name a device and a segment
+ *                     shape (device name, CU count, packed words W, R_L, R_U,
+ *                     consistency, matrix-core operands, jobs and samples per
+ *                     job) and whose values are the chosen configuration.
+ *                     Segments whose key is present take the stored choice
+ *                     without timing; the others are timed, and the file is
+ *                     rewritten (via a temporary file and a rename) with the
+ *                     new entries added.  A missing file counts as empty.
+ * The plan keeps the job array's pointers, so the handles and buffers must
+ * outlive it.  Synchronous.  EINVAL: bad job (NULL handle, n/K mismatch),
+ * a tuning cache that is not such a JSON object.  EUNSUPPORTED: a job whose
+ * system is RSR_SYS_HOST_CALLBACK (host work cannot run inside the graph). */
+rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
+                           const char* tune_cache, rsr_plan** out);
 /* Launches the plan's graph on the context stream (asynchronous). */
 rsr_status rsr_plan_run(rsr_plan* plan);
 /* Synchronises and copies the per-job estimates (host [n_jobs]) and, if
@@ -337,6 +385,16 @@ rsr_status rsr_plan_run(rsr_plan* plan);
  * sum of n*K floats). */
 rsr_status rsr_plan_results(rsr_plan* plan, rsr_estimate_t* est, float* G_host);
 rsr_status rsr_plan_destroy(rsr_plan* plan);
+
+/* ---- testing ---------------------------------------------------------------- */
+
+/* Failure injection for tests of the error paths: after `after` more
+ * successful device or pinned-host allocations made by the library (on any
+ * context), the next one fails as if the device were out of memory (the call
+ * that made it returns RSR_ENOMEM and releases what it had allocated); later
+ * allocations succeed again.  A negative `after` disarms it.  Not
+ * thread-safe with respect to concurrent library calls. */
+rsr_status rsr_debug_fail_alloc(int64_t after);
 
 #ifdef __cplusplus
 }

@@ -261,7 +261,7 @@ int or_phi_st(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, in
 }
 
 /* ------------------------------------------------------------------------- */
-/* System function: global connectivity (section 4.3) and its levels (4.4)     */
+/* System function: global connectivity (section 4.2) and its levels (4.5)     */
 /* ------------------------------------------------------------------------- */
 /* Number of nodes reachable from node 0 over the edges with x_e >= 1, edge
  * `skip` left out (skip = -1: none).  Plain queue BFS. */

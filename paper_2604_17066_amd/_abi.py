@@ -18,6 +18,7 @@ RSR_UNKNOWN_ONLY, RSR_ALL = 0, 1
 RSR_SYS_ST_CONNECTIVITY = 1
 RSR_SYS_GLOBAL_CONNECTIVITY = 2
 RSR_SYS_MAX_FLOW = 3
+RSR_SYS_HOST_CALLBACK = 4
 RSR_MAX_K = 16
 RSR_MAX_BITS = 4096
 RSR_MAX_NODES = 4096
@@ -33,12 +34,18 @@ class rsr_estimate_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+# int32_t (*phi)(const uint8_t* x, int32_t n, void* user)
+PHI_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32,
+                          ctypes.c_void_p)
+
+
 class rsr_system_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
                 ("n_edges", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("edge_u", ctypes.POINTER(ctypes.c_int32)),
                 ("edge_v", ctypes.POINTER(ctypes.c_int32)),
-                ("source", ctypes.c_int32), ("sink", ctypes.c_int32), ("level", ctypes.c_int32)]
+                ("source", ctypes.c_int32), ("sink", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("phi", PHI_FN), ("user", ctypes.c_void_p)]
 
 
 class rsr_job(ctypes.Structure):
@@ -76,6 +83,7 @@ SIGNATURES = {
     "rsr_thresholds": (ctypes.c_int, [_i32, _i32, _vp, _vp]),
     "rsr_model_create": (ctypes.c_int, [_vp, _i32, _i32, _vp, _pp]),
     "rsr_model_destroy": (ctypes.c_int, [_vp]),
+    "rsr_model_update": (ctypes.c_int, [_vp, _vp]),
     "rsr_refs_create": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp, _i64, _pp]),
     "rsr_refs_destroy": (ctypes.c_int, [_vp]),
     "rsr_refs_consistent": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
@@ -86,13 +94,15 @@ SIGNATURES = {
     "rsr_eval_unknown": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]),
     "rsr_estimate": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(rsr_estimate_t)]),
     "rsr_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "rsr_importance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp]),
     "rsr_boundary_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "rsr_stage1": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                   _i64, _vp]),
-    "rsr_plan_create": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_job), _i32, _i32, _pp]),
+    "rsr_plan_create": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_job), _i32, ctypes.c_char_p, _pp]),
     "rsr_plan_run": (ctypes.c_int, [_vp]),
     "rsr_plan_results": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_estimate_t), _vp]),
     "rsr_plan_destroy": (ctypes.c_int, [_vp]),
+    "rsr_debug_fail_alloc": (ctypes.c_int, [_i64]),
 }
 
 _lib = None

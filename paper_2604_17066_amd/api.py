@@ -5,6 +5,7 @@ Functions keep the C names (rsr_sample, rsr_classify, rsr_eval_unknown,
 rsr_estimate, rsr_grad); the small classes own the C handles.
 """
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -67,6 +68,15 @@ class Model:
     def words(self):
         return int(A.lib().rsr_words(self.n, self.K))
 
+    def update(self, p):
+        """rsr_model_update: new probabilities of the same shape, uploaded on the
+        context stream without allocating."""
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+        if p.shape != (self.n, self.K):
+            raise ValueError(f"p must be [{self.n}][{self.K}]")
+        self.ctx.check(A.lib().rsr_model_update(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+        self.p = p
+
     def close(self):
         if getattr(self, "h", None):
             A.lib().rsr_model_destroy(self.h)
@@ -115,21 +125,41 @@ class Refs:
 class System:
     """rsr_system: s-t connectivity of a graph at a level (kind "st"), global
     connectivity at level 1 (connected) or 2 (two-edge-connected) (kind
-    "global"), or max s-t flow >= level with capacities = states (kind
-    "flow")."""
+    "global"), max s-t flow >= level with capacities = states (kind "flow"),
+    or any coherent system function given as a host callback (kind
+    "callback": `phi` maps a uint8 state vector [n] to the system state, and
+    Phi = [phi(x) >= level]; `graph` may then be None, with n given)."""
 
-    def __init__(self, ctx, graph, K=2, level=1, kind="st"):
-        eu = np.ascontiguousarray(graph["edge_u"], dtype=np.int32)
-        ev = np.ascontiguousarray(graph["edge_v"], dtype=np.int32)
-        code = {"st": A.RSR_SYS_ST_CONNECTIVITY, "global": A.RSR_SYS_GLOBAL_CONNECTIVITY,
-                "flow": A.RSR_SYS_MAX_FLOW}[kind]
-        desc = A.rsr_system_desc(
-            code, int(graph["n_nodes"]), eu.size, int(K),
-            eu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-            ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-            int(graph.get("source", 0)), int(graph.get("sink", 0)), int(level))
+    def __init__(self, ctx, graph, K=2, level=1, kind="st", phi=None, n=None):
+        self._phi_fn = None
+        if kind == "callback":
+            if phi is None or n is None:
+                raise ValueError("a callback system needs phi and n")
+            n = int(n)
+
+            def trampoline(x_ptr, n_c, _user):
+                x = np.ctypeslib.as_array(x_ptr, shape=(n_c,)).copy()
+                try:
+                    return int(phi(x))
+                except Exception:   # an exception cannot cross the C ABI
+                    return -1
+
+            self._phi_fn = A.PHI_FN(trampoline)
+            desc = A.rsr_system_desc(A.RSR_SYS_HOST_CALLBACK, 0, n, int(K), None, None, 0, 0,
+                                     int(level), self._phi_fn, None)
+        else:
+            eu = np.ascontiguousarray(graph["edge_u"], dtype=np.int32)
+            ev = np.ascontiguousarray(graph["edge_v"], dtype=np.int32)
+            code = {"st": A.RSR_SYS_ST_CONNECTIVITY, "global": A.RSR_SYS_GLOBAL_CONNECTIVITY,
+                    "flow": A.RSR_SYS_MAX_FLOW}[kind]
+            desc = A.rsr_system_desc(
+                code, int(graph["n_nodes"]), eu.size, int(K),
+                eu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                int(graph.get("source", 0)), int(graph.get("sink", 0)), int(level))
+            n = eu.size
         self.kind = kind
-        self.ctx, self.n, self.K, self.level = ctx, eu.size, int(K), int(level)
+        self.ctx, self.n, self.K, self.level = ctx, int(n), int(K), int(level)
         h = ctypes.c_void_p()
         ctx.check(A.lib().rsr_system_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)))
         self.h = h
@@ -192,6 +222,13 @@ def rsr_grad(ctx, model, samples, Y, N, G=None, counts=None, want_counts=False):
     ctx.check(A.lib().rsr_grad(ctx.h, model.h, _ptr(samples), _ptr(Y), int(N), _ptr(G),
                                _ptr(counts)))
     return (G, counts) if want_counts else G
+
+
+def rsr_importance(ctx, model, samples, Y, N, I=None):
+    """Binary Birnbaum importance dP/dp_i (K = 2) as fp32 [n]."""
+    I = torch.empty(model.n, dtype=torch.float32, device=ctx.device) if I is None else I
+    ctx.check(A.lib().rsr_importance(ctx.h, model.h, _ptr(samples), _ptr(Y), int(N), _ptr(I)))
+    return I
 
 
 def rsr_boundary_search(ctx, system, samples, N, picks, rows=None, side=None):
@@ -271,7 +308,9 @@ def stage2(ctx, model, refs, system, N, seed, stream_id=0, first=0, form=A.RSR_A
 class Plan:
     """rsr_plan over a list of jobs.  Each job is a dict with keys model, refs,
     system, seed, N, buffers (a Buffers) and optionally stream_id and grad
-    (default True: the job's gradient goes to buffers.G)."""
+    (default True: the job's gradient goes to buffers.G).  tune: False (no
+    timing, default configurations), True (time every segment), or the path
+    of a JSON tuning cache (reuse stored choices, time and store the rest)."""
 
     def __init__(self, ctx, jobs, tune=True):
         self.ctx = ctx
@@ -285,8 +324,13 @@ class Plan:
                                b.G.data_ptr() if jb.get("grad", True) else None)
         self._arr = arr
         h = ctypes.c_void_p()
-        ctx.check(A.lib().rsr_plan_create(ctx.h, arr, len(self.jobs), 1 if tune else 0,
-                                          ctypes.byref(h)))
+        if tune is True:
+            cache = b""
+        elif tune is False or tune is None:
+            cache = None
+        else:
+            cache = os.fsencode(tune)
+        ctx.check(A.lib().rsr_plan_create(ctx.h, arr, len(self.jobs), cache, ctypes.byref(h)))
         self.h = h
 
     def run(self):

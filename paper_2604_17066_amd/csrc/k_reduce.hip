@@ -420,6 +420,33 @@ __global__ __launch_bounds__(kBlock) void k_grad_finalize(const uint32_t* __rest
     }
 }
 
+// Binary Birnbaum importance from the same partials (K = 2, one plane): one
+// wavefront per component i adds a(0) = #{Y = 1} and a(1) = #{Y = 1, x_i = 1};
+// c1 = a(1), c0 = a(0) - a(1), and I[i] = c1 / (N p1) - c0 / (N p0) with both
+// quotients in fp64 (0 where p = 0), the difference rounded once to fp32.
+__global__ __launch_bounds__(kBlock) void k_importance_finalize(
+    const uint32_t* __restrict__ partial, const uint32_t* __restrict__ ypart, int bx,
+    const double* __restrict__ p, int n, int64_t N, float* __restrict__ I) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;
+    unsigned long long a0 = 0, a1 = 0;
+    const uint32_t* col = partial + static_cast<int64_t>(i >> 5) * bx * 32 + (i & 31);
+    for (int b = lane; b < bx; b += 64) {
+        a0 += ypart[b];
+        a1 += col[static_cast<int64_t>(b) * 32];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) {
+        const double Nd = static_cast<double>(N);
+        const double p0 = p[2 * i], p1 = p[2 * i + 1];
+        const double g1 = p1 > 0.0 ? static_cast<double>(a1) / (Nd * p1) : 0.0;
+        const double g0 = p0 > 0.0 ? static_cast<double>(a0 - a1) / (Nd * p0) : 0.0;
+        I[i] = static_cast<float>(g1 - g0);
+    }
+}
+
 // Copies every job's gradient into one buffer (out + job.g_off), so a plan
 // returns all gradients with a single device-to-host copy.
 __global__ __launch_bounds__(kBlock) void k_gather_G(const JobDev* __restrict__ jobs, int nK,
@@ -471,6 +498,22 @@ hipError_t launch_counts_vec(hipStream_t st, const uint8_t* d_flags, const uint8
     hipLaunchKernelGGL(k_counts_vec, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
                        d_flags, d_Y, N, reinterpret_cast<unsigned long long*>(d_partial),
                        reinterpret_cast<unsigned long long*>(d_counters), d_ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_importance(hipStream_t st, int n, const double* d_p64, const uint32_t* d_samples,
+                             const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_I) {
+    const int W = plane_words(n);
+    const int64_t bx = grad_blocks(N);
+    uint32_t* ypart = d_partial + static_cast<int64_t>(W) * bx * 32;
+    hipLaunchKernelGGL(k_grad_bits, dim3(static_cast<unsigned>(bx), W, 1), dim3(kBlock), 0, st,
+                       d_samples, d_Y, N, d_partial, ypart, nullptr, int64_t{0});
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int waves_per_block = kBlock / 64;
+    hipLaunchKernelGGL(k_importance_finalize, dim3((n + waves_per_block - 1) / waves_per_block),
+                       dim3(kBlock), 0, st, d_partial, ypart, static_cast<int>(bx), d_p64, n, N,
+                       d_I);
     return hipGetLastError();
 }
 

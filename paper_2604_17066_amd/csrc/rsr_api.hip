@@ -16,6 +16,54 @@
 using rsr::plane_words;
 using rsr::sample_words;
 
+namespace rsr {
+
+// Allocations left before the injected failure (rsr_debug_fail_alloc); < 0:
+// none armed.
+static int64_t g_fail_countdown = -1;
+
+static bool injected_failure() {
+    if (g_fail_countdown < 0) return false;
+    if (g_fail_countdown == 0) {
+        g_fail_countdown = -1;
+        return true;
+    }
+    --g_fail_countdown;
+    return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (injected_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc(void** p, size_t bytes) {
+    if (injected_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+rsr_status ensure_list(rsr_ctx* ctx, int64_t N) {
+    if (ctx->ws.list_cap >= N) return RSR_OK;
+    if (ctx->ws.list) {
+        hipError_t e = hipFree(ctx->ws.list);
+        ctx->ws.list = nullptr;
+        ctx->ws.list_cap = 0;
+        if (e != hipSuccess) return hip_error(ctx, e, "hipFree(unknown list)");
+    }
+    hipError_t e = dev_malloc(&ctx->ws.list, sizeof(int32_t) * static_cast<size_t>(N));
+    if (e != hipSuccess) return hip_error(ctx, e, "unknown-sample list");
+    ctx->ws.list_cap = N;
+    return RSR_OK;
+}
+
+}  // namespace rsr
+
 namespace {
 
 struct DeviceGuard {
@@ -87,17 +135,6 @@ void compute_thresholds(int32_t n, int32_t K, const double* p, uint64_t* C) {
     }
 }
 
-rsr_status ensure_list(rsr_ctx* ctx, int64_t N) {
-    if (ctx->ws.list_cap >= N) return RSR_OK;
-    if (ctx->ws.list) {
-        RSR_HIP(ctx, hipFree(ctx->ws.list));
-        ctx->ws.list = nullptr;
-        ctx->ws.list_cap = 0;
-    }
-    RSR_HIP(ctx, hipMalloc(&ctx->ws.list, sizeof(int32_t) * static_cast<size_t>(N)));
-    ctx->ws.list_cap = N;
-    return RSR_OK;
-}
 
 // A reference set is consistent when no upper row lies below a lower row:
 // then no sample can be dominated on both sides and the LABEL cascade may stop
@@ -113,8 +150,8 @@ rsr_status check_consistency(rsr_ctx* ctx, rsr_refs* refs, const std::vector<uin
         for (int w = 0; w < W; ++w) cols[static_cast<size_t>(w) * RU + r] = up[r * WR + w];
     uint32_t* d_cols = nullptr;
     uint8_t* d_flags = nullptr;
-    hipError_t e = hipMalloc(&d_cols, sizeof(uint32_t) * cols.size());
-    if (e == hipSuccess) e = hipMalloc(&d_flags, static_cast<size_t>(RU));
+    hipError_t e = rsr::dev_malloc(&d_cols, sizeof(uint32_t) * cols.size());
+    if (e == hipSuccess) e = rsr::dev_malloc(&d_flags, static_cast<size_t>(RU));
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_cols, cols.data(), sizeof(uint32_t) * cols.size(),
                            hipMemcpyHostToDevice, ctx->stream);
@@ -139,20 +176,65 @@ rsr_status check_consistency(rsr_ctx* ctx, rsr_refs* refs, const std::vector<uin
     return RSR_OK;
 }
 
+// Byte offsets of a model's device arrays in its single allocation (and in
+// its pinned staging buffer): thresholds u64 [n][K-1], probabilities f64
+// [n][K], sampler threshold halves i32 [ceil(n/8)*8][K-1][2], probabilities
+// f32 [n][K].  Every offset is a multiple of 8.
+struct ModelLayout {
+    size_t thresh, p64, half, p32, total;
+    ModelLayout(int n, int K) {
+        const size_t nn = static_cast<size_t>(n), k1 = static_cast<size_t>(K - 1);
+        const size_t n_pad = (nn + 7) / 8 * 8;
+        thresh = 0;
+        p64 = thresh + sizeof(uint64_t) * nn * k1;
+        half = p64 + sizeof(double) * nn * K;
+        p32 = half + sizeof(int32_t) * n_pad * k1 * 2;
+        total = p32 + sizeof(float) * nn * K;
+    }
+};
+
+// The host images of a model's arrays (p already validated).  The sampler
+// form of a threshold C is a pair (gt, eq) on the high 16 bits of a uniform
+// word u: u >= C is true when (u >> 16) > gt and needs the low half only when
+// (u >> 16) == eq; padding components never set a bit.
+void fill_model_stage(const ModelLayout& L, int n, int K, const double* p, void* stage) {
+    char* base = static_cast<char*>(stage);
+    uint64_t* C = reinterpret_cast<uint64_t*>(base + L.thresh);
+    compute_thresholds(n, K, p, C);
+    std::memcpy(base + L.p64, p, sizeof(double) * static_cast<size_t>(n) * K);
+    int32_t* half = reinterpret_cast<int32_t*>(base + L.half);
+    const size_t n_pad = (static_cast<size_t>(n) + 7) / 8 * 8;
+    for (size_t i = 0; i < n_pad; ++i)
+        for (int s = 0; s < K - 1; ++s) {
+            int32_t gt = 0x7FFFFFFF, eq = -1;
+            if (i < static_cast<size_t>(n)) {
+                const uint64_t c = C[i * (K - 1) + s];
+                const int32_t ch = static_cast<int32_t>(c >> 16);
+                const bool low_zero = (c & 0xFFFFu) == 0;
+                gt = low_zero ? ch - 1 : ch;
+                eq = low_zero ? -1 : ch;
+            }
+            half[(i * (K - 1) + s) * 2] = gt;
+            half[(i * (K - 1) + s) * 2 + 1] = eq;
+        }
+    float* pf = reinterpret_cast<float*>(base + L.p32);
+    for (size_t i = 0; i < static_cast<size_t>(n) * K; ++i) pf[i] = static_cast<float>(p[i]);
+}
+
 rsr_status ensure_cascade(rsr_ctx* ctx, int W, int64_t N) {
     const int64_t words = 2 * static_cast<int64_t>(W) * N, idx = 4 * N;
     if (ctx->ws.casc_words_cap < words) {
         if (ctx->ws.casc_words) RSR_HIP(ctx, hipFree(ctx->ws.casc_words));
         ctx->ws.casc_words = nullptr;
         ctx->ws.casc_words_cap = 0;
-        RSR_HIP(ctx, hipMalloc(&ctx->ws.casc_words, sizeof(uint32_t) * static_cast<size_t>(words)));
+        RSR_HIP(ctx, rsr::dev_malloc(&ctx->ws.casc_words, sizeof(uint32_t) * static_cast<size_t>(words)));
         ctx->ws.casc_words_cap = words;
     }
     if (ctx->ws.casc_index_cap < idx) {
         if (ctx->ws.casc_index) RSR_HIP(ctx, hipFree(ctx->ws.casc_index));
         ctx->ws.casc_index = nullptr;
         ctx->ws.casc_index_cap = 0;
-        RSR_HIP(ctx, hipMalloc(&ctx->ws.casc_index, sizeof(int32_t) * static_cast<size_t>(idx)));
+        RSR_HIP(ctx, rsr::dev_malloc(&ctx->ws.casc_index, sizeof(int32_t) * static_cast<size_t>(idx)));
         ctx->ws.casc_index_cap = idx;
     }
     return RSR_OK;
@@ -205,14 +287,14 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
         return RSR_EHIP;
     }
     ctx->cu_count = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
     rsr_status st = RSR_OK;
-    if (hipMalloc(&ctx->ws.counters, sizeof(uint64_t) * 16) != hipSuccess ||
-        hipMalloc(&ctx->ws.casc_counters, sizeof(uint64_t) * 16) != hipSuccess ||
-        hipMalloc(&ctx->ws.count_part, sizeof(uint64_t) * rsr::kMaxReduceBlocks * 8) != hipSuccess ||
-        hipMalloc(&ctx->ws.grad_part, sizeof(uint32_t) * (static_cast<size_t>(RSR_MAX_BITS) + 1) *
-                                          rsr::kMaxGradBlocks) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&ctx->ws.host_counts), sizeof(uint64_t) * 16,
-                      hipHostMallocDefault) != hipSuccess)
+    if (rsr::dev_malloc(&ctx->ws.counters, sizeof(uint64_t) * 16) != hipSuccess ||
+        rsr::dev_malloc(&ctx->ws.casc_counters, sizeof(uint64_t) * 16) != hipSuccess ||
+        rsr::dev_malloc(&ctx->ws.count_part, sizeof(uint64_t) * rsr::kMaxReduceBlocks * 8) != hipSuccess ||
+        rsr::dev_malloc(&ctx->ws.grad_part, sizeof(uint32_t) * (static_cast<size_t>(RSR_MAX_BITS) + 1) *
+                                                rsr::kMaxGradBlocks) != hipSuccess ||
+        rsr::host_malloc(&ctx->ws.host_counts, sizeof(uint64_t) * 16) != hipSuccess)
         st = RSR_ENOMEM;
     // counters[15] is the ticket of the one-launch counts kernel, which
     // expects it at zero and leaves it there.
@@ -239,6 +321,12 @@ rsr_status rsr_ctx_destroy(rsr_ctx* ctx) {
     if (ctx->ws.count_part) (void)hipFree(ctx->ws.count_part);
     if (ctx->ws.grad_part) (void)hipFree(ctx->ws.grad_part);
     if (ctx->ws.host_counts) (void)hipHostFree(ctx->ws.host_counts);
+    const rsr::CallbackStage& cb = ctx->ws.cb;
+    if (cb.d_words) (void)hipFree(cb.d_words);
+    if (cb.d_bytes) (void)hipFree(cb.d_bytes);
+    if (cb.h_words) (void)hipHostFree(cb.h_words);
+    if (cb.h_bytes) (void)hipHostFree(cb.h_bytes);
+    if (cb.h_index) (void)hipHostFree(cb.h_index);
     delete ctx;
     return RSR_OK;
 }
@@ -252,40 +340,29 @@ rsr_status rsr_model_create(rsr_ctx* ctx, int32_t n, int32_t K, const double* p,
     rsr_status st = validate_probs(ctx, n, K, p);
     if (st != RSR_OK) return st;
     DeviceGuard g(ctx->device);
-    std::vector<uint64_t> C(static_cast<size_t>(n) * (K - 1));
-    compute_thresholds(n, K, p, C.data());
-    std::vector<float> pf(static_cast<size_t>(n) * K);
-    for (size_t i = 0; i < pf.size(); ++i) pf[i] = static_cast<float>(p[i]);
-    const size_t n_pad = (static_cast<size_t>(n) + 7) / 8 * 8;
-    std::vector<int32_t> half(n_pad * (K - 1) * 2);
-    for (size_t i = 0; i < n_pad; ++i)
-        for (int s = 0; s < K - 1; ++s) {
-            int32_t gt = 0x7FFFFFFF, eq = -1;
-            if (i < static_cast<size_t>(n)) {
-                const uint64_t c = C[i * (K - 1) + s];
-                const int32_t ch = static_cast<int32_t>(c >> 16);
-                const bool low_zero = (c & 0xFFFFu) == 0;
-                gt = low_zero ? ch - 1 : ch;
-                eq = low_zero ? -1 : ch;
-            }
-            half[(i * (K - 1) + s) * 2] = gt;
-            half[(i * (K - 1) + s) * 2 + 1] = eq;
-        }
     rsr_model* m = new (std::nothrow) rsr_model();
     if (!m) return fail(ctx, RSR_ENOMEM, "host allocation");
     m->ctx = ctx;
     m->n = n;
     m->K = K;
-    hipError_t e = hipMalloc(&m->d_thresh, sizeof(uint64_t) * C.size());
-    if (e == hipSuccess) e = hipMalloc(&m->d_half, sizeof(int32_t) * half.size());
-    if (e == hipSuccess) e = hipMalloc(&m->d_p, sizeof(float) * pf.size());
-    if (e == hipSuccess)
-        e = hipMemcpy(m->d_thresh, C.data(), sizeof(uint64_t) * C.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(m->d_half, half.data(), sizeof(int32_t) * half.size(),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(m->d_p, pf.data(), sizeof(float) * pf.size(), hipMemcpyHostToDevice);
+    const ModelLayout L(n, K);
+    m->mem_bytes = L.total;
+    hipError_t e = rsr::dev_malloc(&m->d_mem, L.total);
+    if (e == hipSuccess) e = rsr::host_malloc(&m->h_stage, L.total);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->staged, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        rsr_model_destroy(m);
+        return hip_fail(ctx, e, "rsr_model_create allocation");
+    }
+    char* base = static_cast<char*>(m->d_mem);
+    m->d_thresh = reinterpret_cast<uint64_t*>(base + L.thresh);
+    m->d_p64 = reinterpret_cast<double*>(base + L.p64);
+    m->d_half = reinterpret_cast<int32_t*>(base + L.half);
+    m->d_p = reinterpret_cast<float*>(base + L.p32);
+    fill_model_stage(L, n, K, p, m->h_stage);
+    e = hipMemcpyAsync(m->d_mem, m->h_stage, L.total, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(m->staged, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(m->staged);
     if (e != hipSuccess) {
         rsr_model_destroy(m);
         return hip_fail(ctx, e, "rsr_model_create upload");
@@ -294,12 +371,32 @@ rsr_status rsr_model_create(rsr_ctx* ctx, int32_t n, int32_t K, const double* p,
     return RSR_OK;
 }
 
+rsr_status rsr_model_update(rsr_model* m, const double* p) {
+    if (!m) return RSR_EINVAL;
+    rsr_ctx* ctx = m->ctx;
+    rsr_status st = validate_probs(ctx, m->n, m->K, p);
+    if (st != RSR_OK) return st;
+    DeviceGuard g(ctx->device);
+    // The previous upload must have left the staging buffer before it is
+    // overwritten (normally long done: any synchronising call since then
+    // has waited for it).
+    RSR_HIP(ctx, hipEventSynchronize(m->staged));
+    fill_model_stage(ModelLayout(m->n, m->K), m->n, m->K, p, m->h_stage);
+    RSR_HIP(ctx, hipMemcpyAsync(m->d_mem, m->h_stage, m->mem_bytes, hipMemcpyHostToDevice,
+                                ctx->stream));
+    RSR_HIP(ctx, hipEventRecord(m->staged, ctx->stream));
+    return RSR_OK;
+}
+
 rsr_status rsr_model_destroy(rsr_model* m) {
     if (!m) return RSR_EINVAL;
     DeviceGuard g(m->ctx->device);
-    if (m->d_thresh) (void)hipFree(m->d_thresh);
-    if (m->d_half) (void)hipFree(m->d_half);
-    if (m->d_p) (void)hipFree(m->d_p);
+    if (m->staged) {
+        (void)hipEventSynchronize(m->staged);
+        (void)hipEventDestroy(m->staged);
+    }
+    if (m->d_mem) (void)hipFree(m->d_mem);
+    if (m->h_stage) (void)hipHostFree(m->h_stage);
     delete m;
     return RSR_OK;
 }
@@ -444,7 +541,7 @@ rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower,
     hipError_t e = hipSuccess;
     auto upload = [&](void** dst, const void* src, size_t bytes) {
         if (e != hipSuccess || bytes == 0) return;
-        e = hipMalloc(dst, bytes);
+        e = rsr::dev_malloc(dst, bytes);
         if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     };
     upload(reinterpret_cast<void**>(&refs->d_lower_nbits), lo.data(), sizeof(uint32_t) * lo.size());
@@ -511,6 +608,24 @@ rsr_status rsr_refs_destroy(rsr_refs* refs) {
 rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system** out) {
     if (!ctx || !out || !d) return RSR_EINVAL;
     *out = nullptr;
+    if (d->kind == RSR_SYS_HOST_CALLBACK) {
+        if (!d->phi) return fail(ctx, RSR_EINVAL, "RSR_SYS_HOST_CALLBACK without phi");
+        if (d->n_edges <= 0 || d->K < 2) return fail(ctx, RSR_EINVAL, "n must be > 0 and K >= 2");
+        if (d->K > RSR_MAX_K || static_cast<int64_t>(d->n_edges) * (d->K - 1) > RSR_MAX_BITS)
+            return fail(ctx, RSR_EUNSUPPORTED, "n*(K-1) exceeds RSR_MAX_BITS or K > RSR_MAX_K");
+        if (d->level < 1) return fail(ctx, RSR_EINVAL, "level must be >= 1");
+        rsr_system* s = new (std::nothrow) rsr_system();
+        if (!s) return fail(ctx, RSR_ENOMEM, "host allocation");
+        s->ctx = ctx;
+        s->kind = d->kind;
+        s->n_edges = d->n_edges;
+        s->K = d->K;
+        s->level = d->level;
+        s->phi = d->phi;
+        s->user = d->user;
+        *out = s;
+        return RSR_OK;
+    }
     if (d->kind != RSR_SYS_ST_CONNECTIVITY && d->kind != RSR_SYS_GLOBAL_CONNECTIVITY &&
         d->kind != RSR_SYS_MAX_FLOW)
         return fail(ctx, RSR_EINVAL, "unknown system kind");
@@ -560,7 +675,7 @@ rsr_status rsr_system_create(rsr_ctx* ctx, const rsr_system_desc* d, rsr_system*
     s->level = d->level;
     s->source = global ? 0 : d->source;
     s->sink = global ? 0 : d->sink;
-    hipError_t e = hipMalloc(&s->d_edges, sizeof(uint32_t) * packed.size());
+    hipError_t e = rsr::dev_malloc(&s->d_edges, sizeof(uint32_t) * packed.size());
     if (e == hipSuccess)
         e = hipMemcpy(s->d_edges, packed.data(), sizeof(uint32_t) * packed.size(),
                       hipMemcpyHostToDevice);
@@ -654,10 +769,12 @@ rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t*
     if (which == RSR_UNKNOWN_ONLY && !d_flags)
         return fail(ctx, RSR_EINVAL, "d_flags is NULL with RSR_UNKNOWN_ONLY");
     DeviceGuard g(ctx->device);
+    if (sys->kind == RSR_SYS_HOST_CALLBACK)
+        return rsr::eval_callback(ctx, sys, d_samples, N, d_flags, which, d_Y, d_n_evaluated);
     uint64_t* counter = ctx->ws.counters + 8;
     const rsr::SegSrc seg = rsr::single_src(d_samples, N, const_cast<uint8_t*>(d_flags), d_Y);
     if (which == RSR_UNKNOWN_ONLY) {
-        rsr_status st = ensure_list(ctx, N);
+        rsr_status st = rsr::ensure_list(ctx, N);
         if (st != RSR_OK) return st;
         RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, counter, 1, 0));
         RSR_HIP(ctx, rsr::launch_label(ctx->stream, seg, ctx->ws.list, counter, ctx->cu_count * 16));
@@ -676,6 +793,10 @@ rsr_status rsr_boundary_search(rsr_ctx* ctx, const rsr_system* sys, const uint32
     if (!sys || !d_samples || !d_pick || !d_rows || !d_side)
         return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0 || N > 0x7FFFFFFFll) return fail(ctx, RSR_EINVAL, "N must be in 1..2^31-1");
+    if (sys->kind == RSR_SYS_HOST_CALLBACK) {
+        DeviceGuard g(ctx->device);
+        return rsr::boundary_callback(ctx, sys, d_samples, N, d_pick, n_pick, d_rows, d_side);
+    }
     if (rsr::boundary_lds_bytes(sys) > 64 * 1024)
         return fail(ctx, RSR_EUNSUPPORTED, "graph too large for the boundary search");
     DeviceGuard g(ctx->device);
@@ -732,6 +853,23 @@ rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samp
     DeviceGuard g(ctx->device);
     RSR_HIP(ctx, rsr::launch_grad(ctx->stream, model->n, model->K, model->d_p, d_samples, d_Y, N,
                                   ctx->ws.grad_part, d_G, d_counts));
+    return RSR_OK;
+}
+
+rsr_status rsr_importance(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
+                          const uint8_t* d_Y, int64_t N, float* d_I) {
+    if (!ctx) return RSR_EINVAL;
+    if (!model || !d_samples || !d_Y || !d_I) return fail(ctx, RSR_EINVAL, "NULL argument");
+    if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
+    if (model->K != 2) return fail(ctx, RSR_EINVAL, "the Birnbaum importance needs K = 2");
+    DeviceGuard g(ctx->device);
+    RSR_HIP(ctx, rsr::launch_importance(ctx->stream, model->n, model->d_p64, d_samples, d_Y, N,
+                                        ctx->ws.grad_part, d_I));
+    return RSR_OK;
+}
+
+rsr_status rsr_debug_fail_alloc(int64_t after) {
+    rsr::g_fail_countdown = after < 0 ? -1 : after;
     return RSR_OK;
 }
 

@@ -25,6 +25,33 @@ constexpr int kMaxGradBlocks = 64;
 constexpr int kMaxMfmaSteps = 20;   // int8 form: 64 k per step, 1280 bits
 constexpr int kMaxMfma4Steps = 10;  // FP4 form: 128 k per step, 1280 bits
 
+// Every device and pinned-host allocation of the library goes through these
+// two, so that rsr_debug_fail_alloc can make a chosen one fail.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t host_malloc(void** p, size_t bytes);
+template <class T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+    return dev_malloc(reinterpret_cast<void**>(p), bytes);
+}
+template <class T>
+inline hipError_t host_malloc(T** p, size_t bytes) {
+    return host_malloc(reinterpret_cast<void**>(p), bytes);
+}
+
+// Staging of a host-callback system function (rsr_callback.hip): gathered
+// sample words and system-function results on the device and in pinned host
+// memory, grown on demand.
+struct CallbackStage {
+    uint32_t* d_words = nullptr;  // [count][W] sample-major
+    uint32_t* h_words = nullptr;  // pinned copy
+    int64_t words_cap = 0;
+    uint8_t* d_bytes = nullptr;   // [count] results / [count][n] rows
+    uint8_t* h_bytes = nullptr;   // pinned copy
+    int64_t bytes_cap = 0;
+    int64_t* h_index = nullptr;   // pinned [count] picks
+    int64_t index_cap = 0;
+};
+
 struct Workspace {
     uint64_t* counters = nullptr;      // 16 u64 device counters
     uint64_t* count_part = nullptr;    // [kMaxReduceBlocks][8] u64 partial counts
@@ -36,6 +63,7 @@ struct Workspace {
     uint32_t* casc_words = nullptr;    // 2 x [W][N] u32 (cascade)
     int32_t* casc_index = nullptr;     // 2 x [N] i32 indices, then 2 x [N] u32 match words
     int64_t casc_words_cap = 0, casc_index_cap = 0;
+    CallbackStage cb;
 };
 
 }  // namespace rsr
@@ -46,12 +74,20 @@ struct rsr_ctx {
     std::string err;
     rsr::Workspace ws;
     int cu_count = 0;
+    std::string arch;  // gcnArchName of the device
 };
 
 struct rsr_model {
     rsr_ctx* ctx = nullptr;
     int n = 0, K = 0;
+    // One device allocation holds the four arrays below, one pinned host
+    // buffer of the same layout stages their updates.
+    void* d_mem = nullptr;
+    void* h_stage = nullptr;
+    size_t mem_bytes = 0;
+    hipEvent_t staged = nullptr;   // recorded after the last staged upload
     uint64_t* d_thresh = nullptr;  // [n][K-1]
+    double* d_p64 = nullptr;       // [n][K] the probabilities as given
     // Sampler form of the thresholds, [ceil(n/8)*8][K-1] pairs (gt, eq) of
     // int32 on the high 16 bits of the uniform word u: u >= C is decided true
     // by (u >> 16) > gt, and needs the low half only when (u >> 16) == eq.
@@ -86,7 +122,10 @@ struct rsr_system {
     rsr_ctx* ctx = nullptr;
     int kind = RSR_SYS_ST_CONNECTIVITY;
     int n_nodes = 0, n_edges = 0, K = 0, level = 0, source = 0, sink = 0;
-    uint32_t* d_edges = nullptr;  // [n_edges] packed (u | v << 16)
+    uint32_t* d_edges = nullptr;  // [n_edges] packed (u | v << 16); graph systems only
+    // RSR_SYS_HOST_CALLBACK: the system state of a state vector, on the host.
+    int32_t (*phi)(const uint8_t* x, int32_t n, void* user) = nullptr;
+    void* user = nullptr;
 };
 
 namespace rsr {
@@ -262,6 +301,29 @@ hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uin
                        const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,
                        uint64_t* d_counts, const JobDev* jobs = nullptr, int n_jobs = 1);
 hipError_t launch_gather_G(hipStream_t st, const JobDev* jobs, int n_jobs, int nK, float* out);
+// Binary Birnbaum importance I[i] = c1 / (N p1) - c0 / (N p0), fp64 then
+// rounded to fp32 (k_reduce.hip); d_partial as for launch_grad.
+hipError_t launch_importance(hipStream_t st, int n, const double* d_p64, const uint32_t* d_samples,
+                             const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_I);
+
+// Error recording shared by the translation units of the ABI.
+inline rsr_status set_error(rsr_ctx* ctx, rsr_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+inline rsr_status hip_error(rsr_ctx* ctx, hipError_t e, const char* what) {
+    return set_error(ctx, e == hipErrorOutOfMemory ? RSR_ENOMEM : RSR_EHIP,
+                     std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+// Grows the context's unknown-sample list to at least N entries.
+rsr_status ensure_list(rsr_ctx* ctx, int64_t N);
+// Host-callback system function (rsr_callback.hip): Stage-2 evaluation and
+// the componentwise boundary search with Phi evaluated on the host.
+rsr_status eval_callback(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples, int64_t N,
+                         const uint8_t* d_flags, int which, uint8_t* d_Y, uint64_t* d_n_evaluated);
+rsr_status boundary_callback(rsr_ctx* ctx, const rsr_system* sys, const uint32_t* d_samples,
+                             int64_t N, const int64_t* d_pick, int64_t n_pick, uint8_t* d_rows,
+                             uint8_t* d_side);
 hipError_t launch_sample_jobs(hipStream_t st, int n, int K, const JobDev* jobs,
                               const int64_t* offsets, int n_jobs, int64_t total, int grid_cap);
 hipError_t launch_copy_u64(hipStream_t st, const uint64_t* src, uint64_t* dst, int count);

@@ -17,8 +17,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,6 +44,111 @@ struct Segment {
     Choice choice = kCascade;
     rsr::CascadeShape shape;
     float tuned_ms = 0.0f;
+};
+
+// One entry of the tuning cache: the configuration chosen for a segment shape.
+struct TuneEntry {
+    int choice = 0, first = 0, growth = 0, split = 0, tail = 0;
+    double ms = 0.0;
+};
+
+// The tuning cache file is one JSON object: keys are segment-shape strings,
+// values are objects of numbers {"choice", "first", "growth", "split", "tail",
+// "ms"}.  This reader accepts exactly that (strings without escapes) and
+// returns false on anything else.
+class CacheReader {
+  public:
+    explicit CacheReader(const std::string& t) : t_(t) {}
+    bool parse(std::map<std::string, TuneEntry>& out) {
+        ws();
+        if (!eat('{')) return false;
+        ws();
+        if (eat('}')) return tail();
+        for (;;) {
+            std::string key;
+            if (!str(key)) return false;
+            ws();
+            if (!eat(':')) return false;
+            ws();
+            TuneEntry e;
+            if (!entry(e)) return false;
+            out[key] = e;
+            ws();
+            if (eat(',')) {
+                ws();
+                continue;
+            }
+            if (eat('}')) return tail();
+            return false;
+        }
+    }
+
+  private:
+    const std::string& t_;
+    size_t i_ = 0;
+    void ws() {
+        while (i_ < t_.size() && std::isspace(static_cast<unsigned char>(t_[i_]))) ++i_;
+    }
+    bool eat(char c) {
+        if (i_ < t_.size() && t_[i_] == c) {
+            ++i_;
+            return true;
+        }
+        return false;
+    }
+    bool tail() {
+        ws();
+        return i_ == t_.size();
+    }
+    bool str(std::string& s) {
+        if (!eat('"')) return false;
+        const size_t b = i_;
+        while (i_ < t_.size() && t_[i_] != '"') {
+            if (t_[i_] == '\\' || static_cast<unsigned char>(t_[i_]) < 0x20) return false;
+            ++i_;
+        }
+        if (i_ >= t_.size()) return false;
+        s = t_.substr(b, i_ - b);
+        ++i_;
+        return true;
+    }
+    bool num(double& v) {
+        const char* b = t_.c_str() + i_;
+        char* e = nullptr;
+        v = std::strtod(b, &e);
+        if (e == b || !std::isfinite(v)) return false;
+        i_ += static_cast<size_t>(e - b);
+        return true;
+    }
+    bool entry(TuneEntry& e) {
+        if (!eat('{')) return false;
+        int seen = 0;
+        ws();
+        if (eat('}')) return false;
+        for (;;) {
+            std::string k;
+            double v = 0.0;
+            ws();
+            if (!str(k)) return false;
+            ws();
+            if (!eat(':')) return false;
+            ws();
+            if (!num(v)) return false;
+            if (k == "choice") e.choice = static_cast<int>(v), seen |= 1;
+            else if (k == "first") e.first = static_cast<int>(v), seen |= 2;
+            else if (k == "growth") e.growth = static_cast<int>(v), seen |= 4;
+            else if (k == "split") e.split = static_cast<int>(v), seen |= 8;
+            else if (k == "tail") e.tail = static_cast<int>(v), seen |= 16;
+            else if (k == "ms") e.ms = v, seen |= 32;
+            else return false;
+            ws();
+            if (eat(',')) continue;
+            if (eat('}')) break;
+            return false;
+        }
+        return seen == 63 && e.choice >= kCascade && e.choice <= kMfma4PerJob &&
+               (e.choice != kCascade || (e.first >= 1 && e.growth >= 2 && e.split >= 1));
+    }
 };
 
 }  // namespace
@@ -164,6 +273,52 @@ hipError_t enqueue_rest(const rsr_plan* p, int si, hipStream_t st) {
     return e;
 }
 
+// Tuning-cache key of a segment: the device and every property of the
+// segment that the timing depends on.
+std::string segment_key(const rsr_ctx* ctx, const Segment& s) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s/cu%d/W%d/RL%lld/RU%lld/c%d/f%d/J%zu/T%lld/M%lld",
+                  ctx->arch.c_str(), ctx->cu_count, s.W, static_cast<long long>(s.refs->R_L),
+                  static_cast<long long>(s.refs->R_U), s.refs->consistent ? 1 : 0,
+                  s.refs->KS4 > 0 ? 1 : 0, s.jobs.size(), static_cast<long long>(s.total),
+                  static_cast<long long>(s.max_N));
+    return buf;
+}
+
+bool choice_runs(const Segment& s) {
+    switch (s.choice) {
+        case kCascade: return s.refs->consistent && (!s.shape.mfma_tail || s.refs->KS4 > 0);
+        case kBitsPerJob: return true;
+        case kMfmaPerJob: return s.refs->KS > 0;
+        case kMfma4PerJob: return s.refs->KS4 > 0;
+    }
+    return false;
+}
+
+rsr_status write_cache(rsr_ctx* ctx, const std::string& path,
+                       const std::map<std::string, TuneEntry>& cache) {
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return pfail(ctx, RSR_EINVAL, "cannot write tuning cache " + tmp);
+    std::fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto& kv : cache) {
+        const TuneEntry& e = kv.second;
+        std::fprintf(f,
+                     "  \"%s\": {\"choice\": %d, \"first\": %d, \"growth\": %d, \"split\": %d, "
+                     "\"tail\": %d, \"ms\": %.6g}%s\n",
+                     kv.first.c_str(), e.choice, e.first, e.growth, e.split, e.tail, e.ms,
+                     ++k < cache.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) {
+        std::remove(tmp.c_str());
+        return pfail(ctx, RSR_EINVAL, "cannot write tuning cache " + path);
+    }
+    return RSR_OK;
+}
+
 // Times candidate classifications of one segment on its own samples (drawn
 // once) and keeps the fastest.  For a consistent reference set the split-round
 // form (popcount or FP4) is chosen first on the default cascade shape, then
@@ -243,8 +398,8 @@ void free_plan(rsr_plan* p) {
 
 extern "C" {
 
-rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, int32_t tune,
-                           rsr_plan** out) {
+rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
+                           const char* tune_cache, rsr_plan** out) {
     if (!ctx || !out) return RSR_EINVAL;
     *out = nullptr;
     if (!jobs || n_jobs <= 0) return pfail(ctx, RSR_EINVAL, "no jobs");
@@ -259,6 +414,24 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
             return pfail(ctx, RSR_EINVAL, "job " + std::to_string(j) + ": n/K mismatch");
         if (jb.model->ctx->device != ctx->device || jb.refs->ctx->device != ctx->device)
             return pfail(ctx, RSR_EINVAL, "job " + std::to_string(j) + ": handle on another device");
+        if (jb.sys->kind == RSR_SYS_HOST_CALLBACK)
+            return pfail(ctx, RSR_EUNSUPPORTED,
+                         "job " + std::to_string(j) + ": host-callback systems cannot run in a plan");
+    }
+    // The tuning cache is read (and checked) before any device work.
+    const bool tune = tune_cache != nullptr;
+    const std::string cache_path = tune_cache ? tune_cache : "";
+    std::map<std::string, TuneEntry> cache;
+    if (!cache_path.empty()) {
+        if (FILE* f = std::fopen(cache_path.c_str(), "rb")) {
+            std::string text;
+            char buf[4096];
+            size_t got;
+            while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+            std::fclose(f);
+            if (!CacheReader(text).parse(cache))
+                return pfail(ctx, RSR_EINVAL, "tuning cache " + cache_path + " is not a valid cache file");
+        }
     }
     rsr_plan* p = new (std::nothrow) rsr_plan();
     if (!p) return pfail(ctx, RSR_ENOMEM, "host allocation");
@@ -343,7 +516,7 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
     p->casc_w = static_cast<int>(max_words);
     hipError_t e = hipSuccess;
     auto dmalloc = [&](void** ptr, size_t bytes) {
-        if (e == hipSuccess) e = hipMalloc(ptr, bytes > 0 ? bytes : 8);
+        if (e == hipSuccess) e = rsr::dev_malloc(ptr, bytes > 0 ? bytes : 8);
     };
     dmalloc(reinterpret_cast<void**>(&p->d_jobs), sizeof(rsr::JobDev) * host_jobs.size());
     dmalloc(reinterpret_cast<void**>(&p->d_offsets), sizeof(int64_t) * host_offsets.size());
@@ -359,11 +532,9 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
     dmalloc(reinterpret_cast<void**>(&p->d_list_counter), sizeof(uint64_t) * 2);
     dmalloc(reinterpret_cast<void**>(&p->d_G_all), sizeof(float) * p->G_total);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&p->h_counts), sizeof(uint64_t) * 8 * n_jobs,
-                          hipHostMallocDefault);
+        e = rsr::host_malloc(&p->h_counts, sizeof(uint64_t) * 8 * n_jobs);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&p->h_G_all), sizeof(float) * (p->G_total + 1),
-                          hipHostMallocDefault);
+        e = rsr::host_malloc(&p->h_G_all, sizeof(float) * (p->G_total + 1));
     if (e == hipSuccess)
         e = hipMemcpy(p->d_jobs, host_jobs.data(), sizeof(rsr::JobDev) * host_jobs.size(),
                       hipMemcpyHostToDevice);
@@ -383,8 +554,37 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs, in
         return phip(ctx, e, "rsr_plan_create sync");
     }
     if (tune) {
+        bool added = false;
         for (size_t si = 0; si < p->segs.size(); ++si) {
+            Segment& sg = p->segs[si];
+            const std::string key = segment_key(ctx, sg);
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                const TuneEntry& te = it->second;
+                sg.choice = static_cast<Choice>(te.choice);
+                sg.shape = rsr::CascadeShape{te.first, te.growth, te.split, te.tail != 0};
+                sg.tuned_ms = static_cast<float>(te.ms);
+                // A stored choice the handle cannot run (no matrix-core
+                // operands, or a cascade on inconsistent rows) is retimed.
+                if (choice_runs(sg)) continue;
+            }
             rsr_status st = tune_segment(p, static_cast<int>(si));
+            if (st != RSR_OK) {
+                free_plan(p);
+                return st;
+            }
+            TuneEntry te;
+            te.choice = sg.choice;
+            te.first = sg.shape.first;
+            te.growth = sg.shape.growth;
+            te.split = sg.shape.split_rows;
+            te.tail = sg.shape.mfma_tail ? 1 : 0;
+            te.ms = sg.tuned_ms;
+            cache[key] = te;
+            added = true;
+        }
+        if (added && !cache_path.empty()) {
+            rsr_status st = write_cache(ctx, cache_path, cache);
             if (st != RSR_OK) {
                 free_plan(p);
                 return st;

@@ -94,11 +94,11 @@ extern "C" rsr_status rsr_stage1(rsr_ctx* ctx, const rsr_model* model, const rsr
     CurrentDevice guard(ctx->device);
     const int64_t N = P.N, B = P.picks;
     DeviceBuffer samples, flags, pick, rows, side;
-    S1_HIP(ctx, hipMalloc(&samples.p, sizeof(uint32_t) * rsr::sample_words(n, K) * static_cast<size_t>(N)));
-    S1_HIP(ctx, hipMalloc(&flags.p, static_cast<size_t>(N)));
-    S1_HIP(ctx, hipMalloc(&pick.p, sizeof(int64_t) * static_cast<size_t>(B)));
-    S1_HIP(ctx, hipMalloc(&rows.p, row * static_cast<size_t>(B)));
-    S1_HIP(ctx, hipMalloc(&side.p, static_cast<size_t>(B)));
+    S1_HIP(ctx, rsr::dev_malloc(&samples.p, sizeof(uint32_t) * rsr::sample_words(n, K) * static_cast<size_t>(N)));
+    S1_HIP(ctx, rsr::dev_malloc(&flags.p, static_cast<size_t>(N)));
+    S1_HIP(ctx, rsr::dev_malloc(&pick.p, sizeof(int64_t) * static_cast<size_t>(B)));
+    S1_HIP(ctx, rsr::dev_malloc(&rows.p, row * static_cast<size_t>(B)));
+    S1_HIP(ctx, rsr::dev_malloc(&side.p, static_cast<size_t>(B)));
     std::vector<uint8_t> rows_h(row * static_cast<size_t>(B)), side_h(static_cast<size_t>(B));
     uint64_t* d_total = ctx->ws.counters + 12;
     uint64_t* h_total = ctx->ws.host_counts + 12;

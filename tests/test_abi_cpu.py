@@ -113,3 +113,38 @@ def test_null_arguments_rejected_without_device():
     assert lib.rsr_eval_unknown(None, None, None, 10, None, 0, None, None) == A.RSR_EINVAL
     assert lib.rsr_grad(None, None, None, None, 10, None, None) == A.RSR_EINVAL
     assert lib.rsr_plan_run(None) == A.RSR_EINVAL
+
+
+def _status_functions():
+    return [name for name, (res, _) in A.SIGNATURES.items()
+            if res is ctypes.c_int and name != "rsr_debug_fail_alloc"]
+
+
+@pytest.mark.parametrize("name", _status_functions())
+def test_every_entry_point_rejects_null_arguments(name):
+    """Every entry point that returns an rsr_status returns RSR_EINVAL, without
+    touching a device, when its handles and pointers are NULL and its counts
+    zero (the context, or the first handle, is checked before anything else)."""
+    fn = getattr(A.lib(), name)
+    args = []
+    for t in A.SIGNATURES[name][1]:
+        if t in (ctypes.c_void_p, ctypes.c_char_p) or isinstance(t, type(ctypes.POINTER(ctypes.c_int))):
+            args.append(None)
+        else:
+            args.append(0)
+    assert fn(*args) == A.RSR_EINVAL, name
+
+
+def test_every_status_function_is_covered():
+    """The parametrised test above covers every declared function returning an
+    rsr_status (the header and the binding agree, checked above)."""
+    text = open(os.path.join(ROOT, "include", "rsr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = set(re.findall(r"rsr_status\s+(rsr_[a-z_0-9]+)\s*\(", text))
+    assert declared - {"rsr_debug_fail_alloc"} == set(_status_functions())
+
+
+def test_fail_alloc_hook_arms_and_disarms():
+    lib = A.lib()
+    assert lib.rsr_debug_fail_alloc(3) == A.RSR_OK
+    assert lib.rsr_debug_fail_alloc(-1) == A.RSR_OK

@@ -1,4 +1,4 @@
-"""GPU parity of global connectivity (sections 4.3-4.4): system-function
+"""GPU parity of global connectivity (sections 4.2 and 4.5): system-function
 evaluation at levels 1 (connected) and 2 (two-edge-connected), the boundary
 search, the whole Stage-2 path with brute-force reference sets, and the
 Stage-1 loop, all against the oracle on the same seeded samples."""

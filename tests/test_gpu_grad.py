@@ -95,3 +95,87 @@ def test_importance_against_crn_differences(rsr_ctx):
         tol = 3.0 * math.hypot(se_fd, se_sf[i])
         print(f"i={i}: score-function {grad[i]:.5f}, CRN difference {fd:.5f}, tol {tol:.5f}")
         assert abs(fd - grad[i]) <= tol
+
+
+def test_importance_config_size_against_oracle(rsr_ctx):
+    """Binary Birnbaum importance on the graph2 workload at its full size
+    (N = 1e6, 1e4 + 1e4 rows): rsr_importance against the fp64 oracle's
+    G[i][1] - G[i][0], held to |I32 - I64| <= 1e-5 (|G1| + |G0|) (the
+    difference can cancel, so the bound is relative to the two terms); the
+    library forms both quotients in fp64, so the result is the fp64 value
+    rounded once."""
+    cfg = WL.configs.graph2()
+    N = cfg["N"]
+    model = R.Model(rsr_ctx, cfg["p"])
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
+    system = R.System(rsr_ctx, cfg["graph"])
+    est, buf = R.stage2(rsr_ctx, model, refs, system, N, cfg["seed"], grad=False)
+    I = R.rsr_importance(rsr_ctx, model, buf.samples, buf.Y, N)
+    torch.cuda.synchronize()
+    x = oracle.sample(cfg["p"], cfg["seed"], 0, 0, N)
+    Y, _ = oracle.eval_unknown(cfg["graph"], x, None, which=1)
+    np.testing.assert_array_equal(buf.Y.cpu().numpy(), Y)
+    _, G = oracle.grad(cfg["p"], x, Y)
+    I64 = G[:, 1] - G[:, 0]
+    I32 = I.cpu().numpy().astype(np.float64)
+    err = np.abs(I32 - I64)
+    bound = 1e-5 * (np.abs(G[:, 1]) + np.abs(G[:, 0]))
+    print("max |I32 - I64| / (|G1| + |G0|) =", np.max(err / np.maximum(bound * 1e5, 1e-300)))
+    assert np.all(err <= bound)
+    np.testing.assert_array_equal(I.cpu().numpy(), I64.astype(np.float32))
+
+
+def test_model_update_equals_fresh_model(rsr_ctx):
+    """rsr_model_update followed by the hot path gives exactly what a model
+    created with the new probabilities gives, and the update is ordered after
+    work enqueued before it."""
+    cfg = WL.configs.graph2(N=50_000)
+    N = cfg["N"]
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"][:2000], cfg["upper"][:2000])
+    system = R.System(rsr_ctx, cfg["graph"])
+    rng = np.random.default_rng(5)
+    q = WL.configs.binary_model(rng.uniform(0.7, 0.99, cfg["n"]))
+    m = R.Model(rsr_ctx, cfg["p"])
+    xs_old = R.rsr_sample(rsr_ctx, m, 9, 0, 0, N)      # enqueued before the update
+    m.update(q)
+    est_u, buf_u = R.stage2(rsr_ctx, m, refs, system, N, 9)
+    fresh = R.Model(rsr_ctx, q)
+    est_f, buf_f = R.stage2(rsr_ctx, fresh, refs, system, N, 9)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(buf_u.samples.cpu().numpy(), buf_f.samples.cpu().numpy())
+    np.testing.assert_array_equal(buf_u.G.cpu().numpy(), buf_f.G.cpu().numpy())
+    assert est_u == est_f
+    old = R.rsr_sample(rsr_ctx, R.Model(rsr_ctx, cfg["p"]), 9, 0, 0, N)
+    np.testing.assert_array_equal(xs_old.cpu().numpy(), old.cpu().numpy())
+    with pytest.raises(R.RSRError):
+        m.update(np.full((cfg["n"], 2), 0.7))      # rows do not sum to 1
+    est_again, _ = R.stage2(rsr_ctx, m, refs, system, N, 9)
+    assert est_again == est_u                    # a rejected update leaves the model as it was
+
+
+def test_autograd_float32_multistate_rows(rsr_ctx):
+    """A float32 [n][3] probability tensor (rows sum to 1 only up to float32
+    rounding) is accepted; the gradient is rsr_grad's G at the rows
+    renormalised in fp64."""
+    cfg = WL.configs.multi(N=1, R_per_level=2000)
+    n = cfg["n"]
+    lv = cfg["levels"][1]
+    refs = R.Refs(rsr_ctx, n, 3, lv["lower"], lv["upper"])
+    system = R.System(rsr_ctx, cfg["graph"], K=3, level=1)
+    p32 = torch.tensor(cfg["p"], dtype=torch.float32, requires_grad=True)
+    assert float(torch.abs(p32.detach().double().sum(dim=1) - 1.0).max()) > 1e-9
+    N = 1 << 16
+    P = R.rsr_probability(p32, refs, system, N, seed=4, rsr_ctx=rsr_ctx)
+    P.backward()
+    pm = p32.detach().double()
+    pm = (pm / pm.sum(dim=1, keepdim=True)).numpy()
+    m = R.Model(rsr_ctx, pm)
+    est, buf = R.stage2(rsr_ctx, m, refs, system, N, 4)
+    torch.cuda.synchronize()
+    assert float(P) == est["P"]
+    np.testing.assert_array_equal(p32.grad.numpy(), buf.G.cpu().numpy())
+    # A second forward reuses the pooled model (no new model is created).
+    pool = rsr_ctx.__dict__["_autograd_models"][(n, 3)]
+    assert len(pool) == 1
+    P2 = R.rsr_probability(p32, refs, system, N, seed=4, rsr_ctx=rsr_ctx)
+    assert float(P2) == float(P) and len(pool) == 0

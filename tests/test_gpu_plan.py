@@ -85,7 +85,7 @@ def test_plan_replays_identical(rsr_ctx):
     jobs, _ = _small_batch(rsr_ctx, n_scen=3, graphs=(0, 2))
     plan = R.Plan(rsr_ctx, jobs, tune=False)
     ref = None
-    for rep in range(4):
+    for rep in range(10):
         plan.run()
         est, grads = plan.results()
         snap = ([dict(e) for e in est], [g.copy() for g in grads],
@@ -131,3 +131,47 @@ def test_plan_inconsistent_segment_uses_precedence(rsr_ctx):
         cnt = oracle.counts(fl, Y)
         assert est[k]["n_L"] == int(cnt[0]) and est[k]["n_u_up"] == int(cnt[4])
     plan.close()
+
+
+def test_plan_tuning_cache(rsr_ctx, tmp_path):
+    """A tuning-cache file: the first plan times every segment and writes one
+    entry per segment; a second plan over the same shapes reads them back
+    (no timing: it is created much faster) and gives identical results; a
+    malformed file is rejected with RSR_EINVAL."""
+    import json
+    import time
+    path = tmp_path / "tune.json"
+    jobs, systems = _small_batch(rsr_ctx, n_scen=2, graphs=(0, 2))
+    t0 = time.perf_counter()
+    plan = R.Plan(rsr_ctx, jobs, tune=str(path))
+    t_tuned = time.perf_counter() - t0
+    entries = json.loads(path.read_text())
+    assert len(entries) == len(systems)
+    for key, e in entries.items():
+        assert key.startswith(torch.cuda.get_device_properties(0).gcnArchName)
+        assert set(e) == {"choice", "first", "growth", "split", "tail", "ms"}
+    plan.run()
+    est1, g1 = plan.results()
+    flags1 = [_np(jb["buffers"].flags).copy() for jb in jobs]
+    plan.close()
+    t0 = time.perf_counter()
+    plan = R.Plan(rsr_ctx, jobs, tune=str(path))
+    t_cached = time.perf_counter() - t0
+    assert json.loads(path.read_text()) == entries
+    plan.run()
+    est2, g2 = plan.results()
+    plan.close()
+    print(f"plan creation: tuned {t_tuned:.3f} s, from the cache {t_cached:.3f} s")
+    assert t_cached < t_tuned
+    for a, b in zip(est1, est2):
+        assert a["P"] == b["P"] and a["n_u"] == b["n_u"]
+    for a, b in zip(g1, g2):
+        np.testing.assert_array_equal(a, b)
+    for jb, f in zip(jobs, flags1):
+        np.testing.assert_array_equal(_np(jb["buffers"].flags), f)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"x": {"choice": 0}}')
+    with pytest.raises(R.RSRError) as ei:
+        R.Plan(rsr_ctx, jobs, tune=str(bad))
+    assert ei.value.status == R.RSR_EINVAL
+    assert bad.read_text() == '{"x": {"choice": 0}}'

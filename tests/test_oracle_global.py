@@ -1,5 +1,5 @@
-"""Pins of the oracle's global-connectivity system function (section 4.3)
-and its three levels (section 4.4): closed forms on cycles, trees and
+"""Pins of the oracle's global-connectivity system function (section 4.2)
+and its three levels (section 4.5): closed forms on cycles, trees and
 parallel edges; an independent all-pairs edge-disjoint-path count (unit
 capacity max flow, Menger) on small graphs; the matrix-tree theorem for the
 number of minimal survival states; and boundary searches that land on

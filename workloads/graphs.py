@@ -1,5 +1,5 @@
 """Random geometric graphs in the unit square (the paper's test networks,
-section 2.3.3 "Limitations of decomposition-based approaches", exist only as
+section 2.4 "Limitations of decomposition-based approaches", exist only as
 figures, so seeded graphs of the same node and edge counts stand in)."""
 import numpy as np
 from scipy.sparse import csr_matrix
