@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--only-legs", default="", metavar="LIST",
                     help="comma-separated legs (scaling, multi, batched, stage1, global, flow) to "
                          "run alone, without the step; prints their results as one JSON line")
-    ap.add_argument("--batched-scale", type=float, default=0.25,
+    ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="reference rows of the batched workload, as a fraction of its sizes")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -163,6 +163,10 @@ def main():
         return float(np.mean([a.elapsed_time(b) for a, b in cev]))
 
     W = model.words
+    # Work per test of the contraction: 2 Kpad ops, Kpad = the packed bits
+    # rounded up to 64.  The FP4 instruction contracts 128 k at a time, so its
+    # issued work is 2 KP4 (bits rounded up to 128); that figure is reported
+    # beside the algorithmic one, never as it.
     KP = 64 * ((32 * W + 63) // 64)
     KP4 = 128 * ((32 * W + 127) // 128)
     kern = {}
@@ -176,16 +180,20 @@ def main():
     # Matrix-core form: 2 KP int8 operations per test (KP = packed bits rounded to 64).
     kern["mfma"]["count_achieved"] = float(tests) * 2 * KP / (kern["mfma"]["count_ms"] * 1e-3)
     kern["mfma"]["count_frac"] = kern["mfma"]["count_achieved"] / MFMA_I8_PEAK_OPS
-    # FP4 form: 2 KP4 flops per test (KP4 = packed bits rounded to 128), dense FP4 peak.
-    kern["mfma_fp4"]["count_achieved"] = float(tests) * 2 * KP4 / (kern["mfma_fp4"]["count_ms"] * 1e-3)
+    # FP4 form: 2 KP flops per test against the dense FP4 peak (the issued
+    # instruction work, 2 KP4 per test, is reported separately).
+    kern["mfma_fp4"]["count_achieved"] = float(tests) * 2 * KP / (kern["mfma_fp4"]["count_ms"] * 1e-3)
     kern["mfma_fp4"]["count_frac"] = kern["mfma_fp4"]["count_achieved"] / MFMA_FP4_PEAK_FLOPS
+    kern["mfma_fp4"]["issued_ops_per_test"] = 2 * KP4
+    kern["mfma_fp4"]["issued_frac"] = (float(tests) * 2 * KP4 / (kern["mfma_fp4"]["count_ms"] * 1e-3)
+                                       / MFMA_FP4_PEAK_FLOPS)
     for k, v in kern.items():
         log(f"{k}: COUNT {v['count_ms']:.3f} ms ({v['count_frac'] * 100:.1f}% of peak), "
             f"LABEL {v['label_ms']:.3f} ms")
     # LABEL classification of the step's own form, timed alone.
     label_ms = time_classify(R.RSR_LABEL, form)
     peaks = {"popcount": VALU_PEAK_OPS, "mfma": MFMA_I8_PEAK_OPS, "mfma_fp4": MFMA_FP4_PEAK_FLOPS}
-    ops_per_test = {"popcount": W, "mfma": 2 * KP, "mfma_fp4": 2 * KP4}
+    ops_per_test = {"popcount": W, "mfma": 2 * KP, "mfma_fp4": 2 * KP}
     # The roofline kernel is the COUNT-mode classification of the form the step
     # uses; the automatic form classifies in COUNT mode with the FP4 form.
     dom = args.form if args.form != "auto" else "mfma_fp4"
@@ -238,12 +246,34 @@ def main():
     }
     log("stages: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in step_kernels.items()))
 
+    # Plain Monte Carlo on the GPU (the system function on every sample, no
+    # reference states): the method's own baseline, on the same samples.
+    Y_plain = torch.empty(N, dtype=torch.uint8, device=ctx.device)
+    def run_plain():
+        ctx.check(lib.rsr_eval_unknown(h, system.h, P(buf.samples), N, None, R.RSR_ALL,
+                                       P(Y_plain), None))
+    plain_ms = _event_ms(run_plain, st_reps)
+    plain_P = int(Y_plain.sum(dtype=torch.int64).item()) / N
+    step_kernels["plain_mc_eval_all"] = {
+        "ms": plain_ms, "phi_evals_per_s": N / (plain_ms * 1e-3), "P": plain_P,
+        "equals_rsr_P": plain_P == est["P"],
+        "rsr_step_speedup": (plain_ms + sample_ms + grad_ms + est_ms) / ms_per_step}
+    log(f"plain MC (BFS on every sample): {plain_ms:.3f} ms, P={plain_P:.6f}")
+
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, R_L + R_U, args.cpu_seconds)
+        # The buffers hold the last pass of the step (same seed every pass).
+        est_now = R.rsr_estimate(ctx, buf.flags, buf.Y, N)
+        G_now, c_now = R.rsr_grad(ctx, model, buf.samples, buf.Y, N, want_counts=True)
+        I_now = R.rsr_importance(ctx, model, buf.samples, buf.Y, N)
+        torch.cuda.synchronize()
+        cpu, parity = oracle_check(cfg, R_L + R_U, args.cpu_seconds, est_now, c_now.cpu().numpy(),
+                                   G_now.cpu().numpy(), I_now.cpu().numpy())
     extra = {}
     if not args.skip_legs:
-        extra["scaling_count_mode"] = scaling_leg(ctx, reps)
+        extra["scaling_count_mode"] = scaling_leg(
+            ctx, reps, None if args.no_cpu_baseline else args.cpu_seconds)
         extra["multi_state"] = multi_leg(ctx, reps)
         extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps)
         extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
@@ -261,7 +291,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u32+fp4",
         "data": "synthetic",
         "config": {
             "workload": "graph2: seeded 119-node / 295-edge random geometric graph, s-t "
@@ -282,6 +312,7 @@ def main():
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "algorithmic_bytes": 4.0 * W * N + (R_L + R_U) * 4.0 * W + N,
             "ops_per_test": ops_per_test[dom],
+            "issued_ops_per_test": 2 * KP4 if dom == "mfma_fp4" else ops_per_test[dom],
             "kernel_ms": count_ms,
         },
         "classify_forms": kern,
@@ -292,6 +323,7 @@ def main():
             "multiple_of_exhaustive_roofline": (tests / (label_ms * 1e-3)) / (VALU_PEAK_OPS / W),
         },
         "cpu_baseline": cpu,
+        "parity": parity,
         **extra,
     }
     print(json.dumps(out), flush=True)
@@ -310,7 +342,7 @@ def _event_ms(fn, reps):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def scaling_leg(ctx, reps):
+def scaling_leg(ctx, reps, cpu_seconds=None):
     """Kernel-only workload (n = 295, 1e5 + 1e5 Bernoulli rows, N = 1e6), every
     classification form in COUNT mode (every test in full) against its
     roofline, and in LABEL mode (these rows are not a consistent reference
@@ -331,7 +363,7 @@ def scaling_leg(ctx, reps):
     KP4 = 128 * ((32 * W + 127) // 128)
     for name, form, ops, peak in (("popcount", R.RSR_POPCOUNT, W, VALU_PEAK_OPS),
                                   ("mfma", R.RSR_MFMA, 2 * KP, MFMA_I8_PEAK_OPS),
-                                  ("mfma_fp4", R.RSR_MFMA_FP4, 2 * KP4, MFMA_FP4_PEAK_FLOPS)):
+                                  ("mfma_fp4", R.RSR_MFMA_FP4, 2 * KP, MFMA_FP4_PEAK_FLOPS)):
         ms = _event_ms(lambda: R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, form, flags=flags),
                        reps)
         ach = tests * ops / (ms * 1e-3)
@@ -340,8 +372,13 @@ def scaling_leg(ctx, reps):
         out[name] = {"kernel_ms": ms, "tests_per_s": tests / (ms * 1e-3), "achieved_TOPs": ach / 1e12,
                      "peak_TOPs": peak / 1e12, "frac": ach / peak, "ops_per_test": ops,
                      "label_ms": label_ms}
+        if name == "mfma_fp4":
+            out[name]["issued_ops_per_test"] = 2 * KP4
+            out[name]["issued_frac"] = tests * 2 * KP4 / (ms * 1e-3) / peak
         log(f"scaling COUNT {name}: {ms:.2f} ms, {ach / peak * 100:.1f}% of peak; "
             f"LABEL {label_ms:.2f} ms")
+    if cpu_seconds:
+        out["cpu_baseline"] = cpu_baseline_scaling(cfg, cpu_seconds)
     return out
 
 
@@ -416,10 +453,24 @@ def stage1_leg(ctx, with_cpu):
     e1.record(st)
     torch.cuda.synchronize()
     search_ms = e0.elapsed_time(e1) / 5
+    # The Stage-2 step of the headline workload with these grown rows in place
+    # of the structural path / cut rows.
+    refs = R.Refs(ctx, cfg["n"], 2, lo, up)
+    N2 = 1_000_000
+    est2, buf2 = R.stage2(ctx, model, refs, system, N2, 2)
+    torch.cuda.synchronize()
+    t1 = _t.perf_counter()
+    for _ in range(10):
+        est2, buf2 = R.stage2(ctx, model, refs, system, N2, 2, buffers=buf2)
+    torch.cuda.synchronize()
+    grown_ms = (_t.perf_counter() - t1) * 1e3 / 10
     out = {"workload": "graph2 (295 edges) from empty reference sets; 1e5 samples and 1024 searches "
                        "per iteration; stop at p_u < 1e-3, 2e4 rows or 100 iterations",
            "loop_s": loop_s, **info, "rows": int(info["R_L"] + info["R_U"]),
-           "boundary_searches_per_s": N / (search_ms * 1e-3), "boundary_search_ms_2e17": search_ms}
+           "boundary_searches_per_s": N / (search_ms * 1e-3), "boundary_search_ms_2e17": search_ms,
+           "stage2_step_grown_rows": {"ms": grown_ms, "N": N2, "P": est2["P"], "p_u": est2["p_u"],
+                                      "nominal_tests_per_s": N2 * (len(lo) + len(up))
+                                      / (grown_ms * 1e-3)}}
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline_boundary(cfg, 9, 256)
     log(f"stage 1: {info['iterations']} iterations, {out['rows']} rows, p_u {info['p_u']:.2e}, "
@@ -531,66 +582,89 @@ def flow_leg(ctx):
     return out
 
 
-def batched_leg(ctx, ref_scale, reps):
-    """64 hazard scenarios x 8 graphs = 512 jobs at N = 2^18 (SE <= 1e-3 for any
-    P): the batched plan (one graph launch) against the plain form (the
-    library's calls job by job, with a host sync per job for its estimate)."""
+def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000)):
+    """64 hazard scenarios x 8 graphs = 512 jobs, at N = 2^18 (SE <= 9.8e-4 <
+    1e-3 for any P) and at N = 1e6: P_sys and the gradient of every job by the
+    batched plan (one graph launch, tuned configurations) against the plain
+    form (the library's calls job by job, with a host synchronisation per job
+    for its estimate), in the library's default (automatic) form and, for
+    reference, in the popcount form.  Plan creation is timed with an empty
+    tuning cache and again with the cache it wrote."""
+    import tempfile
     import time as _t
-    import numpy as np
     import torch
     import paper_2604_17066_amd as R
     import workloads as WL
-    N = 1 << 18
     t0 = _t.time()
-    cfg = WL.configs.batched(n_scen=64, N=N, ref_scale=ref_scale)
+    cfg = WL.configs.batched(n_scen=64, N=1, ref_scale=ref_scale)
     log(f"batched workload built in {_t.time() - t0:.1f}s")
     systems = []
     for sd in cfg["systems"]:
         systems.append((sd, R.Refs(ctx, sd["n"], 2, sd["lower"], sd["upper"]), R.System(ctx, sd["graph"])))
-    jobs = []
-    for jd in cfg["jobs"]:
-        sd, refs, system = systems[jd["system"]]
-        jobs.append({"model": R.Model(ctx, jd["p"]), "refs": refs, "system": system,
-                     "seed": jd["seed"], "N": N, "buffers": R.Buffers(ctx, sd["n"], 2, N)})
+    models = [R.Model(ctx, jd["p"]) for jd in cfg["jobs"]]
+    rows = [r.R_L + r.R_U for _, r, _ in systems]
+    out = {"workload": f"64 hazard scenarios x 8 graphs (50-500 nodes, 120-1250 edges), "
+                       f"{len(cfg['jobs'])} jobs, reference rows x{ref_scale} of 1e3..2e5 per graph "
+                       f"({', '.join(str(r) for r in rows)}); P_sys and gradient per job",
+           "ref_rows": rows}
+    tmp = tempfile.mkdtemp(prefix="rsr_tune_")
+    for N in Ns:
+        jobs = []
+        for jd, m in zip(cfg["jobs"], models):
+            sd, refs, system = systems[jd["system"]]
+            jobs.append({"model": m, "refs": refs, "system": system, "seed": jd["seed"], "N": N,
+                         "buffers": R.Buffers(ctx, sd["n"], 2, N)})
 
-    def plain():
-        out = []
-        for jb in jobs:
-            est, _ = R.stage2(ctx, jb["model"], jb["refs"], jb["system"], N, jb["seed"],
-                              form=R.RSR_POPCOUNT, buffers=jb["buffers"])
-            out.append(est)
-        return out
+        def plain(form):
+            res = []
+            for jb in jobs:
+                est, _ = R.stage2(ctx, jb["model"], jb["refs"], jb["system"], N, jb["seed"],
+                                  form=form, buffers=jb["buffers"])
+                res.append(est)
+            return res
 
-    plain_est = plain()
-    torch.cuda.synchronize()
-    t1 = _t.perf_counter()
-    for _ in range(reps):
-        plain_est = plain()
-    torch.cuda.synchronize()
-    plain_ms = (_t.perf_counter() - t1) * 1e3 / reps
-    t2 = _t.time()
-    plan = R.Plan(ctx, jobs, tune=True)
-    create_s = _t.time() - t2
-    plan.run()
-    est, grads = plan.results()
-    torch.cuda.synchronize()
-    t3 = _t.perf_counter()
-    for _ in range(reps):
-        plan.run()
-        est, grads = plan.results()
-    batched_ms = (_t.perf_counter() - t3) * 1e3 / reps
-    same = all(a["P"] == b["P"] and a["n_u"] == b["n_u"] for a, b in zip(est, plain_est))
-    se = max(e["se"] for e in est)
-    total_tests = float(N) * sum(len(cfg["jobs"]) // len(systems) * (r.R_L + r.R_U)
-                                 for _, r, _ in systems)
-    log(f"batched: plain {plain_ms:.1f} ms, plan {batched_ms:.1f} ms "
-        f"({plain_ms / batched_ms:.2f}x), identical={same}, max SE {se:.2e}")
-    plan.close()
-    return {"workload": f"64 hazard scenarios x 8 graphs (50-500 nodes), {len(jobs)} jobs, N=2^18 each, "
-                        f"reference rows x{ref_scale} of 1e3..2e5 per graph; P_sys and gradient per job",
-            "plain_ms": plain_ms, "batched_ms": batched_ms, "speedup": plain_ms / batched_ms,
-            "plan_create_s": create_s, "identical_estimates": same, "max_se": se,
-            "nominal_tests_per_s_batched": total_tests / (batched_ms * 1e-3)}
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = _t.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            torch.cuda.synchronize()
+            return (_t.perf_counter() - t) * 1e3 / reps, r
+
+        plain_ms, plain_est = timed(lambda: plain(R.RSR_AUTO))
+        pop_ms, _ = timed(lambda: plain(R.RSR_POPCOUNT))
+        cache = f"{tmp}/tune_{N}.json"
+        t2 = _t.time()
+        plan = R.Plan(ctx, jobs, tune=cache)
+        create_s = _t.time() - t2
+        plan.close()
+        t2 = _t.time()
+        plan = R.Plan(ctx, jobs, tune=cache)
+        create_cached_s = _t.time() - t2
+
+        def run_plan():
+            plan.run()
+            return plan.results()[0]
+
+        batched_ms, est = timed(run_plan)
+        same = all(a["P"] == b["P"] and a["n_u"] == b["n_u"] for a, b in zip(est, plain_est))
+        plan.close()
+        se = max(e["se"] for e in est)
+        total_tests = float(N) * sum(len(cfg["jobs"]) // len(systems) * r for r in rows)
+        log(f"batched N={N}: plain (automatic form) {plain_ms:.1f} ms, plain popcount "
+            f"{pop_ms:.1f} ms, plan {batched_ms:.1f} ms ({plain_ms / batched_ms:.2f}x), "
+            f"identical={same}, max SE {se:.2e}, plan creation {create_s:.1f}s "
+            f"({create_cached_s:.2f}s from the tuning cache)")
+        out[f"N{N}"] = {"plain_ms": plain_ms, "plain_popcount_ms": pop_ms, "batched_ms": batched_ms,
+                        "speedup_vs_plain": plain_ms / batched_ms,
+                        "speedup_vs_plain_popcount": pop_ms / batched_ms,
+                        "plan_create_s": create_s, "plan_create_from_cache_s": create_cached_s,
+                        "identical_estimates": same, "max_se": se,
+                        "nominal_tests_per_s_batched": total_tests / (batched_ms * 1e-3)}
+        del jobs
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline_boundary(cfg, seed, count):
@@ -606,30 +680,103 @@ def cpu_baseline_boundary(cfg, seed, count):
             "kind": "oracle", "sample": f"{count} start samples of graph2, {dt:.2f} s"}
 
 
-def cpu_baseline(cfg, R_total, seconds):
-    """The oracle as it stands, on the first N_sub samples of the same workload
-    (same seed), timed over the whole hot path on the host cores."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_check(cfg, R_total, seconds, est, counts, G, I):
+    """The oracle as it stands on the whole graph2 workload (1e6 samples: the
+    hot path's sample, classify, evaluate, estimate and gradient) on all host
+    threads: its time is the CPU baseline, and its counts, P, gradient
+    counts, G (fp32 within 1e-5 of fp64) and binary importance I (within
+    1e-5 (|G1| + |G0|)) are compared with the GPU step's.  The single-thread
+    rate is timed on the first samples of the same workload, sized to about
+    `seconds` / 3 by a pilot run."""
+    import numpy as np
     import oracle
     cores = oracle.get_threads()
     g = cfg["graph"]
+    N = cfg["N"]
 
     def run(n_sub):
         t = time.perf_counter()
         x = oracle.sample(cfg["p"], cfg["seed"], 0, 0, n_sub)
         fl, _, _ = oracle.classify(cfg["lower"], cfg["upper"], x, mode=0)
         Y, _ = oracle.eval_unknown(g, x, fl)
-        oracle.estimate(oracle.counts(fl, Y))
-        oracle.grad(cfg["p"], x, Y)
+        cnt = oracle.counts(fl, Y)
+        oest = oracle.estimate(cnt)
+        c, Gref = oracle.grad(cfg["p"], x, Y)
+        return time.perf_counter() - t, cnt, oest, c, Gref
+
+    t_all, cnt, oest, c, Gref = run(N)
+    log(f"cpu oracle: {N} samples in {t_all:.2f}s on {cores} threads")
+    names = ["n_L", "n_U", "n_u", "n_both", "n_u_up"]
+    counts_ok = all(int(cnt[k]) == int(est[nm]) for k, nm in enumerate(names))
+    P_ok = oest[3] == est["P"]
+    c_ok = bool(np.array_equal(counts.view(np.uint64), c))
+    nz = Gref != 0
+    G_rel = float(np.max(np.abs(G[nz].astype(np.float64) - Gref[nz]) / np.abs(Gref[nz])))
+    G_ok = G_rel <= 1e-5 and bool(np.all(G[~nz] == 0))
+    I64 = Gref[:, 1] - Gref[:, 0]
+    I_err = np.abs(I.astype(np.float64) - I64)
+    I_ok = bool(np.all(I_err <= 1e-5 * (np.abs(Gref[:, 1]) + np.abs(Gref[:, 0]))))
+    parity = {"ok": bool(counts_ok and P_ok and c_ok and G_ok and I_ok),
+              "what": "oracle on all 1e6 samples of the step: counts, P (bit-exact), gradient "
+                      "counts (exact), G (fp32 vs fp64, rel <= 1e-5), binary importance "
+                      "(|I32 - I64| <= 1e-5 (|G1| + |G0|))",
+              "counts": counts_ok, "P": P_ok, "P_oracle": oest[3], "grad_counts": c_ok,
+              "G_max_rel_err": G_rel, "G": G_ok, "importance": I_ok}
+    log(f"parity against the oracle: {parity['ok']} (G max rel err {G_rel:.2e})")
+    oracle.set_threads(1)
+    try:
+        pilot_n = 2000
+        pilot = run(pilot_n)[0]
+        n1 = int(min(N, max(pilot_n, pilot_n * (seconds / 3.0) / max(pilot, 1e-6))))
+        t1 = run(n1)[0]
+    finally:
+        oracle.set_threads(cores)
+    log(f"cpu oracle, one thread: {n1} samples in {t1:.2f}s")
+    cpu = {"value": N * R_total / t_all, "unit": "tests/s", "cores": cores, "kind": "oracle",
+           "sample": f"all {N} samples of the same workload, whole hot path (sample, classify, "
+                     f"evaluate, estimate, gradient), {t_all:.1f} s",
+           "cpu_model": _cpu_model(),
+           "single_thread": {"value": n1 * R_total / t1, "unit": "tests/s", "cores": 1,
+                             "sample": f"first {n1} samples of the same workload, whole hot "
+                                       f"path, {t1:.1f} s"}}
+    return cpu, parity
+
+
+def cpu_baseline_scaling(cfg, seconds):
+    """The oracle's COUNT-mode classification (exact match counts) of the
+    kernel-only workload on its first samples, sized to about `seconds` by a
+    pilot; the rate over the full 1e6 samples is a linear extrapolation."""
+    import oracle
+    cores = oracle.get_threads()
+
+    def run(n_sub):
+        x = oracle.sample(cfg["p"], cfg["seed"], 0, 0, n_sub)
+        t = time.perf_counter()
+        oracle.classify(cfg["lower"], cfg["upper"], x, mode=1)
         return time.perf_counter() - t
 
-    pilot_n = 2000
+    R_total = cfg["lower"].shape[0] + cfg["upper"].shape[0]
+    pilot_n = 256
     pilot = run(pilot_n)
     n_sub = int(min(cfg["N"], max(pilot_n, pilot_n * seconds / max(pilot, 1e-6))))
     t = run(n_sub)
-    log(f"cpu oracle: {n_sub} samples in {t:.2f}s on {cores} threads")
+    log(f"cpu oracle, kernel-only COUNT: {n_sub} samples in {t:.2f}s on {cores} threads")
     return {"value": n_sub * R_total / t, "unit": "tests/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n_sub} of the {cfg['N']} samples of the same workload, whole "
-                      f"hot path (sample, classify, evaluate, estimate, gradient), {t:.1f} s"}
+            "sample": f"first {n_sub} of the {cfg['N']} samples, COUNT-mode classification "
+                      f"against all {R_total} rows, {t:.1f} s; the full workload's time is "
+                      f"extrapolated linearly: {t * cfg['N'] / n_sub:.0f} s",
+            "extrapolated_full_s": t * cfg["N"] / n_sub}
 
 
 if __name__ == "__main__":

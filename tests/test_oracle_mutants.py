@@ -88,7 +88,7 @@ def _run(name, old, new, tmp):
     assert src.count(old) >= 1, f"mutation site not found: {name}"
     path_c = os.path.join(tmp, f"m{abs(hash(name))}.c")
     path_so = path_c[:-2] + ".so"
-    open(path_c, "w").write(src.replace(old, new, 1))
+    open(path_c, "w").write(src.replace(old, new, 1) if old else src)
     subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                     "-o", path_so, path_c, "-lm"], check=True, capture_output=True)
     env = dict(os.environ, RSR_ORACLE_LIB=path_so, OMP_NUM_THREADS="2")
@@ -105,8 +105,17 @@ def _run(name, old, new, tmp):
 
 
 def test_every_mutant_is_killed():
+    """pytest exits with 1 when a test failed (a pin caught the mutant); any
+    other non-zero code (collection or usage error, internal error, no tests)
+    is not a catch.  The unmodified source goes through the same build and run
+    first and must pass."""
     with tempfile.TemporaryDirectory() as tmp:
+        _, rc0 = _run("unmutated", "", "", tmp)
+        assert rc0 == 0, f"the unmutated oracle fails its pins in the harness (rc {rc0})"
         with cf.ThreadPoolExecutor(max_workers=6) as ex:
             results = list(ex.map(lambda kv: _run(kv[0], kv[1][0], kv[1][1], tmp), MUTANTS.items()))
+    caught = {name for name, rc in results if rc == 1 or rc == "timeout"}
+    odd = {name: rc for name, rc in results if name not in caught and rc != 0}
     survivors = [name for name, rc in results if rc == 0]
+    assert not odd, f"mutant runs that ended neither passing nor failing: {odd}"
     assert not survivors, f"mutants not caught by any pin: {survivors}"
