@@ -271,6 +271,23 @@ rsr_status rsr_grad(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samp
 rsr_status rsr_importance(rsr_ctx* ctx, const rsr_model* model, const uint32_t* d_samples,
                           const uint8_t* d_Y, int64_t N, float* d_I);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rsr_eval_unknown without any allocation.  Same arguments, outputs and
+ * errors as rsr_eval_unknown, except that the list of unclassified samples
+ * and its counter live in a fixed scratch array of the library, one per
+ * device, of 16 MiB + 64 bytes, held until the process ends; so N is limited
+ * to 2^22 samples (EINVAL beyond), and host-callback systems, which stage
+ * samples in allocated host and device memory, are EUNSUPPORTED.  The
+ * counter is cleared by a kernel at the start of every call.  Every call on
+ * one device shares that device's scratch: calls that overlap on one device
+ * (on different streams or from different host threads) race, so the
+ * caller must order them. */
+rsr_status rsr_eval_unknown_noalloc(rsr_ctx* ctx, const rsr_system* sys,
+                                    const uint32_t* d_samples, int64_t N,
+                                    const uint8_t* d_flags, int32_t which, uint8_t* d_Y,
+                                    uint64_t* d_n_evaluated);
+
 /* ---- Stage 1: new reference states -------------------------------------- */
 
 /* Componentwise boundary search (section 3.4, fig. x1x2_find_ref) from the

@@ -92,6 +92,7 @@ SIGNATURES = {
     "rsr_sample": (ctypes.c_int, [_vp, _vp, _u64, _u32, _u64, _i64, _vp]),
     "rsr_classify": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]),
     "rsr_eval_unknown": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]),
+    "rsr_eval_unknown_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]),
     "rsr_estimate": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(rsr_estimate_t)]),
     "rsr_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "rsr_importance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp]),

@@ -296,6 +296,8 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
                                                 rsr::kMaxGradBlocks) != hipSuccess ||
         rsr::host_malloc(&ctx->ws.host_counts, sizeof(uint64_t) * 16) != hipSuccess)
         st = RSR_ENOMEM;
+    if (st == RSR_OK && rsr::noalloc_scratch(device, &ctx->noalloc_scratch) != hipSuccess)
+        st = RSR_EHIP;
     // counters[15] is the ticket of the one-launch counts kernel, which
     // expects it at zero and leaves it there.
     if (st == RSR_OK && hipMemset(ctx->ws.counters, 0, sizeof(uint64_t) * 16) != hipSuccess)

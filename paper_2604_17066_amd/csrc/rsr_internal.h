@@ -75,6 +75,7 @@ struct rsr_ctx {
     rsr::Workspace ws;
     int cu_count = 0;
     std::string arch;  // gcnArchName of the device
+    void* noalloc_scratch = nullptr;  // this device's address of rsr_noalloc.hip's scratch
 };
 
 struct rsr_model {
@@ -305,6 +306,13 @@ hipError_t launch_gather_G(hipStream_t st, const JobDev* jobs, int n_jobs, int n
 // rounded to fp32 (k_reduce.hip); d_partial as for launch_grad.
 hipError_t launch_importance(hipStream_t st, int n, const double* d_p64, const uint32_t* d_samples,
                              const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_I);
+
+// Scratch of rsr_eval_unknown_noalloc (rsr_noalloc.hip): a file-scope device
+// array holding a counter and a list of up to kNoAllocMaxSamples indices.
+constexpr int64_t kNoAllocMaxSamples = int64_t{1} << 22;
+constexpr int RSR_MAX_DEVICES = 64;
+// This device's address of the array, looked up once per device.
+hipError_t noalloc_scratch(int device, void** out);
 
 // Error recording shared by the translation units of the ABI.
 inline rsr_status set_error(rsr_ctx* ctx, rsr_status st, const std::string& msg) {
