@@ -719,7 +719,7 @@ def oracle_check(cfg, R_total, seconds, est, counts, G, I):
     log(f"cpu oracle: {N} samples in {t_all:.2f}s on {cores} threads")
     names = ["n_L", "n_U", "n_u", "n_both", "n_u_up"]
     counts_ok = all(int(cnt[k]) == int(est[nm]) for k, nm in enumerate(names))
-    P_ok = oest[3] == est["P"]
+    P_ok = bool(oest[3] == est["P"])
     c_ok = bool(np.array_equal(counts.view(np.uint64), c))
     nz = Gref != 0
     G_rel = float(np.max(np.abs(G[nz].astype(np.float64) - Gref[nz]) / np.abs(Gref[nz])))
