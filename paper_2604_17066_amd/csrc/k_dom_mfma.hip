@@ -430,6 +430,328 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
     }
 }
 
+// ---- FP4 form on 32 x 32 tiles ------------------------------------------------
+//
+// v_mfma_scale_f32_32x32x64_f8f6f4 contracts 64 k per instruction (twice the
+// rows and samples of the 16 x 16 x 128 form, half its k), so a row of W
+// packed words takes ceil(32 W / 64) steps: the bits rounded up to 64, as in
+// the int8 form, instead of to 128 (295 bits: 320 k instead of 384).  Lane l
+// supplies row / column l % 32 and nibbles j = 0..31 of k = 64 s + 32 (l / 32)
+// + j, i.e. the whole packed word 2 s + l / 32.  The result lane l holds
+// column l % 32 and, in register v, row 8 (v / 4) + 4 (l / 32) + v % 4.
+//
+// Both sides contract +1 nibbles with a constant start of -1/2, so no
+// per-row start is staged: the lower pass contracts NOT t(r) with t(x)
+// (|t(x) & ~t(r)| - 1/2, negative iff x <= r), the upper pass t(r) with the
+// complement of t(x) within the valid bits (|t(r) & ~t(x)| - 1/2, negative
+// iff x >= r).  The complement is formed in registers by XOR with the FP4
+// expansion of the valid-bit mask, since a sample has no pad bits set.
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v16f mfma32_step(v4i a, v4i b, v16f acc) {
+    const v8i a8 = {a.x, a.y, a.z, a.w, 0, 0, 0, 0};
+    const v8i b8 = {b.x, b.y, b.z, b.w, 0, 0, 0, 0};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc, 4, 4, 0, 127, 0, 127);
+}
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+template <bool COUNT>
+__device__ __forceinline__ int fold32(v16f r, int acc) {
+    const v16i ri = __builtin_bit_cast(v16i, r);
+    const v4i q0 = __builtin_shufflevector(ri, ri, 0, 1, 2, 3);
+    const v4i q1 = __builtin_shufflevector(ri, ri, 4, 5, 6, 7);
+    const v4i q2 = __builtin_shufflevector(ri, ri, 8, 9, 10, 11);
+    const v4i q3 = __builtin_shufflevector(ri, ri, 12, 13, 14, 15);
+    if (COUNT) {
+        uint32_t u = static_cast<uint32_t>(acc);
+        u = add_negatives8(q0, u);
+        u = add_negatives8(q1, u);
+        u = add_negatives8(q2, u);
+        u = add_negatives8(q3, u);
+        return static_cast<int>(u);
+    }
+    return min(acc, min(min(min4(q0), min4(q1)), min(min4(q2), min4(q3))));
+}
+
+// Reference tiles (32 rows) per staged group; the double-buffered stage takes
+// 2 * TPS * KS KB of LDS.
+template <int KS>
+constexpr int tiles_per_stage32() {
+    return KS <= 3 ? 10 : KS <= 5 ? 7 : (KS <= 10 ? 3 : 2);
+}
+
+// Sample tiles (32 samples) per wave: B fragments take 4 MT KS VGPRs and the
+// two accumulator sets of the pipelined fold 32 MT (LABEL mode also keeps the
+// vote state, so it allows one tile less from KS = 5 on).
+template <int KS, bool COUNT>
+constexpr int sample_tiles32() {
+    return KS <= 4 ? 4 : KS == 5 ? (COUNT ? 4 : 3) : KS <= 8 ? 3 : KS <= 13 ? 2 : 1;
+}
+
+// A smaller count also built where the grid's last round of blocks matters
+// (see prefer_alt).
+template <int KS>
+constexpr int sample_tiles32_alt() {
+    return KS == 5 ? 2 : 0;
+}
+
+// fold32 over a tile whose rows from `rows` on are padding: their values
+// (which start at -1/2 like every row) are replaced by +1/2 first.  Row of
+// value v in lane half h: 8 (v / 4) + 4 h + v % 4.
+template <bool COUNT>
+__device__ __forceinline__ int fold32_last(v16f r, int acc, int rows, int half) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        if (8 * (v / 4) + 4 * half + v % 4 >= rows) r[v] = 0.5f;
+    return fold32<COUNT>(r, acc);
+}
+
+// One pass over the 32-row tiles of one side (R rows).  acc_out[t] = 8 *
+// matches (COUNT) or the running signed minimum (LABEL) for this lane's
+// column of sample tile t, over this lane's 16 rows of each tile.
+template <int KS, int MT, bool COUNT, int TPS = tiles_per_stage32<KS>()>
+__device__ __forceinline__ void mfma32_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
+                                            int64_t R, v4i* __restrict__ lds, int (&acc_out)[MT],
+                                            const bool (&pre_done)[MT], const bool (&valid)[MT],
+                                            int* vote) {
+    constexpr int kTileV4 = KS * 64;  // operand v4i per reference tile
+    constexpr int kStageV4 = TPS * kTileV4;
+    constexpr int kPerThread = (kStageV4 + kBlock - 1) / kBlock;
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    if (R <= 0) return;
+    const int tiles = static_cast<int>((R + 31) / 32);
+    const int last_rows = static_cast<int>(R - 32 * static_cast<int64_t>(tiles - 1));
+    const int groups = (tiles + TPS - 1) / TPS;
+
+    // Each thread stages the same slots of every group (slot q = element idx
+    // of the group's contiguous fragments).
+    v4i stage[kPerThread];
+    int slot_tile[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int idx = q * kBlock + threadIdx.x;
+        slot_tile[q] = idx < kStageV4 ? idx / kTileV4 : 1 << 30;
+    }
+    auto fetch = [&](int G) {
+        const v4i* src = frag + static_cast<int64_t>(G) * kStageV4 + threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+            v4i v = {0, 0, 0, 0};
+            if (G * TPS + slot_tile[q] < tiles) v = src[q * kBlock];
+            stage[q] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+            const int idx = q * kBlock + threadIdx.x;
+            if (idx < kStageV4) lds[buf * kStageV4 + idx] = stage[q];
+        }
+    };
+
+    const v16f start = v16f{} - 0.5f;
+    v16f prev[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) prev[t] = start;
+    fetch(0);
+    store(0);
+    __syncthreads();
+    for (int G = 0; G < groups; ++G) {
+        const int cur = G & 1;
+        if (G + 1 < groups) fetch(G + 1);
+        const int in_group = tiles - G * TPS < TPS ? tiles - G * TPS : TPS;
+        for (int tt = 0; tt < in_group; ++tt) {
+            __builtin_amdgcn_sched_barrier(0);
+            const v4i* tile = lds + cur * kStageV4 + tt * kTileV4;
+            v4i a[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a[s] = tile[s * 64 + lane];
+            v16f acc[MT];
+            constexpr bool kPrio = KS * MT < 30;
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    acc[t] = mfma32_step(a[s], bf[t][s], s == 0 ? start : acc[t]);
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
+            // The previous tile (a full one: only the last tile can be partial,
+            // and it is folded after the loop).  Before the first tile prev
+            // holds -1/2 starts that no row produced: skip it.
+            if (G + tt > 0) {
+#pragma unroll
+                for (int t = 0; t < MT; ++t) acc_out[t] = fold32<COUNT>(prev[t], acc_out[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < MT; ++t) prev[t] = acc[t];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) asm volatile("" ::"v"(acc_out[t]));
+        }
+        if (G + 1 < groups) store(cur ^ 1);
+        bool leave = false;
+        if (!COUNT) {
+            bool done = true;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                int m = min(acc_out[t], __shfl_xor(acc_out[t], 32));
+                done = done && (!valid[t] || pre_done[t] || m < 0);
+            }
+            const int wave_done = __all(done) ? 1 : 0;
+            if (lane == 0) vote[threadIdx.x >> 6] = wave_done;
+            __syncthreads();
+            int all = 1;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) all &= vote[w];
+            // A pass left early never reaches the last tile: the tile in prev
+            // is full (the last tile can only be in prev after the loop).
+            leave = all != 0 && G + 1 < groups;
+        }
+        __syncthreads();
+        if (leave) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t) acc_out[t] = fold32<COUNT>(prev[t], acc_out[t]);
+            return;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc_out[t] = fold32_last<COUNT>(prev[t], acc_out[t], last_rows, half);
+}
+
+// Valid-bit mask of packed word w of an n-component sample (plane-major
+// thermometer words of PW words each, pad bits 0); 0 past the W words.
+__device__ __forceinline__ uint32_t valid_word(int w, int n, int PW, int W) {
+    if (w >= W) return 0u;
+    const int left = n - 32 * (w % PW);
+    return left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+}
+
+__device__ __forceinline__ v4i expand_word_fp4(uint32_t bits) {
+    v4i f;
+    f.x = expand8_fp4(bits & 0xFFu);
+    f.y = expand8_fp4((bits >> 8) & 0xFFu);
+    f.z = expand8_fp4((bits >> 16) & 0xFFu);
+    f.w = expand8_fp4(bits >> 24);
+    return f;
+}
+
+// Sample operand of the wave's MT sample tiles (32 samples each): lane l holds
+// sample wbase + 32 t + l % 32, and for k-step s its packed word 2 s + l / 32
+// as 32 FP4 nibbles.
+template <int KS, int MT>
+__device__ __forceinline__ void load_samples32(const uint32_t* __restrict__ xs, int64_t stride,
+                                               int64_t count, int W, int64_t wbase, int lane,
+                                               v4i (&bf)[MT][KS], bool (&valid)[MT]) {
+    const int col = lane & 31, half = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int64_t h = wbase + 32 * t + col;
+        valid[t] = h < count;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int w = 2 * s + half;
+            const uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * stride + h] : 0u;
+            bf[t][s] = expand_word_fp4(bits);
+        }
+    }
+}
+
+template <int KS, int MT, bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_dom_fp4x32(
+    const uint32_t* __restrict__ xs, int64_t N, int n, int PW, int W,
+    const v4i* __restrict__ low_frag, int64_t R_L, const v4i* __restrict__ up_frag, int64_t R_U,
+    uint8_t* __restrict__ flags, uint32_t* __restrict__ match) {
+    __shared__ v4i lds[2 * tiles_per_stage32<KS>() * KS * 64];
+    __shared__ int vote[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t wbase = (static_cast<int64_t>(blockIdx.x) * kWaves + wave) * (32 * MT);
+
+    v4i bf[MT][KS];
+    bool valid[MT];
+    load_samples32<KS, MT>(xs, N, N, W, wbase, lane, bf, valid);
+
+    int accL[MT], accU[MT];
+    bool none[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        accL[t] = 0;
+        accU[t] = 0;
+        none[t] = false;
+    }
+    mfma32_pass<KS, MT, COUNT>(bf, low_frag, R_L, lds, accL, none, valid, vote);
+    bool lowered[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        int m = accL[t];
+        if (COUNT) {
+            const uint32_t u = static_cast<uint32_t>(m) +
+                               static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32));
+            m = static_cast<int>(u >> 3);
+        } else {
+            m = min(m, __shfl_xor(m, 32));
+        }
+        accL[t] = m;
+        lowered[t] = COUNT ? false : (m < 0);
+    }
+    bool skip_upper = false;
+    if (!COUNT) {
+        bool done = true;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) done = done && (!valid[t] || lowered[t]);
+        const int wave_done = __all(done) ? 1 : 0;
+        if (lane == 0) vote[wave] = wave_done;
+        __syncthreads();
+        int all = 1;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) all &= vote[w];
+        skip_upper = all != 0;
+        __syncthreads();
+    }
+    if (!skip_upper) {
+        // Upper pass on the complement of the samples within the valid bits.
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const v4i m = expand_word_fp4(valid_word(2 * s + (lane >> 5), n, PW, W));
+#pragma unroll
+            for (int t = 0; t < MT; ++t) bf[t][s] ^= m;
+        }
+        mfma32_pass<KS, MT, COUNT>(bf, up_frag, R_U, lds, accU, lowered, valid, vote);
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        int m = accU[t];
+        if (COUNT) {
+            const uint32_t u = static_cast<uint32_t>(m) +
+                               static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), 32));
+            m = static_cast<int>(u >> 3);
+        } else {
+            m = min(m, __shfl_xor(m, 32));
+        }
+        accU[t] = m;
+    }
+    if (lane < 32) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            if (!valid[t]) continue;
+            const int64_t h = wbase + 32 * t + lane;
+            uint8_t f;
+            if (COUNT) {
+                f = static_cast<uint8_t>((accL[t] ? 1 : 0) | (accU[t] ? 2 : 0));
+                if (match) {
+                    match[2 * h] = static_cast<uint32_t>(accL[t]);
+                    match[2 * h + 1] = static_cast<uint32_t>(accU[t]);
+                }
+            } else {
+                f = static_cast<uint8_t>(lowered[t] ? 1 : (accU[t] < 0 ? 2 : 0));
+            }
+            flags[h] = f;
+        }
+    }
+}
+
 // One chunk of a split LABEL round of the cascade (k_cascade.hip) in the FP4
 // form: the compacted undecided samples (word-major, row stride cstride, their
 // number on the device) against the reference tiles of chunk blockIdx.y of
@@ -636,6 +958,50 @@ hipError_t launch_casc_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* 
     return hipGetLastError();
 }
 
+template <int KS, int MT, bool COUNT>
+hipError_t launch_fp4x32_mt(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
+                            uint8_t* flags, uint32_t* match) {
+    const int64_t per_block = static_cast<int64_t>(kWaves) * 32 * MT;
+    const dim3 grid(static_cast<unsigned>((N + per_block - 1) / per_block));
+    hipLaunchKernelGGL((k_dom_fp4x32<KS, MT, COUNT>), grid, dim3(kBlock), 0, st, xs, N, refs->n,
+                       plane_words(refs->n), refs->W,
+                       reinterpret_cast<const v4i*>(refs->d_lower_frag32), refs->R_L,
+                       reinterpret_cast<const v4i*>(refs->d_upper_frag32), refs->R_U, flags,
+                       match);
+    return hipGetLastError();
+}
+
+// Cost of a sample-tile count: blocks of kWaves * 32 * mt samples, one per CU
+// at a time, each taking time about proportional to mt.
+inline bool prefer_alt32(int64_t N, int cus, int mt, int alt) {
+    if (alt <= 0 || cus <= 0) return false;
+    auto cost = [&](int m) {
+        const int64_t per_block = static_cast<int64_t>(kWaves) * 32 * m;
+        const int64_t blocks = (N + per_block - 1) / per_block;
+        return ((blocks + cus - 1) / cus) * m;
+    };
+    return cost(alt) < cost(mt);
+}
+
+template <int KS, bool COUNT>
+hipError_t launch_fp4x32_mode(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
+                              int cus, uint8_t* flags, uint32_t* match) {
+    constexpr int MT = sample_tiles32<KS, COUNT>();
+    constexpr int ALT = sample_tiles32_alt<KS>();
+    if constexpr (ALT > 0) {
+        if (prefer_alt32(N, cus, MT, ALT))
+            return launch_fp4x32_mt<KS, ALT, COUNT>(st, refs, xs, N, flags, match);
+    }
+    return launch_fp4x32_mt<KS, MT, COUNT>(st, refs, xs, N, flags, match);
+}
+
+template <int KS>
+hipError_t launch_fp4x32_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
+                            int mode, int cus, uint8_t* flags, uint32_t* match) {
+    return mode == RSR_COUNT ? launch_fp4x32_mode<KS, true>(st, refs, xs, N, cus, flags, match)
+                             : launch_fp4x32_mode<KS, false>(st, refs, xs, N, cus, flags, match);
+}
+
 template <int KS, int MT, bool FP4>
 hipError_t launch_mt(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
                      int mode, uint8_t* flags, uint32_t* match) {
@@ -673,11 +1039,14 @@ hipError_t launch_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, i
 hipError_t launch_dom_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t* xs, int64_t N,
                            int mode, bool fp4, int cus, uint8_t* flags, uint32_t* match) {
     if (fp4) {
-        switch (refs->KS4) {
+        // FP4 on 32 x 32 tiles: k-steps of 64, the same count as the int8 form.
+        switch (refs->KS) {
 #define RSR_KS_CASE(k) \
-    case k: return launch_ks<k, true>(st, refs, xs, N, mode, cus, flags, match);
+    case k: return launch_fp4x32_ks<k>(st, refs, xs, N, mode, cus, flags, match);
             RSR_KS_CASE(1) RSR_KS_CASE(2) RSR_KS_CASE(3) RSR_KS_CASE(4) RSR_KS_CASE(5)
             RSR_KS_CASE(6) RSR_KS_CASE(7) RSR_KS_CASE(8) RSR_KS_CASE(9) RSR_KS_CASE(10)
+            RSR_KS_CASE(11) RSR_KS_CASE(12) RSR_KS_CASE(13) RSR_KS_CASE(14) RSR_KS_CASE(15)
+            RSR_KS_CASE(16) RSR_KS_CASE(17) RSR_KS_CASE(18) RSR_KS_CASE(19) RSR_KS_CASE(20)
 #undef RSR_KS_CASE
             default: return hipErrorInvalidValue;
         }

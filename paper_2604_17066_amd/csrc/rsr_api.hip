@@ -477,7 +477,7 @@ rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower,
     const int KS4 = (W * 32 + 127) / 128;
     std::vector<int8_t> lof, upf;
     std::vector<int32_t> loc, upc;
-    std::vector<uint8_t> lof4, upf4;
+    std::vector<uint8_t> lof4, upf4, lof32, upf32;
     std::vector<float> loc4, upc4;
     if (with_mfma) {
         auto frag = [&](const uint32_t* words, int64_t r, int8_t value, std::vector<int8_t>& dst) {
@@ -529,6 +529,27 @@ rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower,
             frag4(up.data() + r * WR, r, 0xA, upf4);  // -1.0
             upc4[r] = static_cast<float>(upc[r]) + 0.5f;  // |t(r)| - 0.5
         }
+        // FP4 operands on 32-row tiles: 64 k per step; lane (half h, row rr)
+        // holds nibbles j = 0..31 for k = 64 s + 32 h + j.  Both sides are +1
+        // nibbles (NOT t(r) for lower rows, t(r) for upper rows); the kernel
+        // starts every row at -1/2 and contracts upper rows with the
+        // complemented samples.
+        auto frag32 = [&](const uint32_t* words, int64_t r, std::vector<uint8_t>& dst) {
+            const int64_t T = r / 32;
+            const int rr = static_cast<int>(r % 32);
+            for (int k = 0; k < W * 32; ++k) {
+                if (!((words[k / 32] >> (k % 32)) & 1u)) continue;
+                const int s = k / 64, o = k % 64;
+                const int lane = (o / 32) * 32 + rr, j = o % 32;
+                dst[((static_cast<size_t>(T) * KS + s) * 64 + lane) * 16 + j / 2] |=
+                    static_cast<uint8_t>(0x2 << (4 * (j % 2)));
+            }
+        };
+        const int64_t TL32 = (R_L + 31) / 32, TU32 = (R_U + 31) / 32;
+        lof32.assign(static_cast<size_t>(TL32) * KS * 1024, 0);
+        upf32.assign(static_cast<size_t>(TU32) * KS * 1024, 0);
+        for (int64_t r = 0; r < R_L; ++r) frag32(lo.data() + r * WR, r, lof32);
+        for (int64_t r = 0; r < R_U; ++r) frag32(up.data() + r * WR, r, upf32);
     }
 
     rsr_refs* refs = new (std::nothrow) rsr_refs();
@@ -556,6 +577,8 @@ rsr_status refs_create(rsr_ctx* ctx, int32_t n, int32_t K, const uint8_t* lower,
         upload(reinterpret_cast<void**>(&refs->d_lower_cinit), loc.data(), sizeof(int32_t) * loc.size());
         upload(reinterpret_cast<void**>(&refs->d_upper_frag), upf.data(), upf.size());
         upload(reinterpret_cast<void**>(&refs->d_upper_cinit), upc.data(), sizeof(int32_t) * upc.size());
+        upload(reinterpret_cast<void**>(&refs->d_lower_frag32), lof32.data(), lof32.size());
+        upload(reinterpret_cast<void**>(&refs->d_upper_frag32), upf32.data(), upf32.size());
         refs->KS4 = KS4;
         upload(reinterpret_cast<void**>(&refs->d_lower_frag4), lof4.data(), lof4.size());
         upload(reinterpret_cast<void**>(&refs->d_lower_cinit4), loc4.data(), sizeof(float) * loc4.size());
@@ -603,6 +626,8 @@ rsr_status rsr_refs_destroy(rsr_refs* refs) {
     if (refs->d_lower_cinit4) (void)hipFree(refs->d_lower_cinit4);
     if (refs->d_upper_frag4) (void)hipFree(refs->d_upper_frag4);
     if (refs->d_upper_cinit4) (void)hipFree(refs->d_upper_cinit4);
+    if (refs->d_lower_frag32) (void)hipFree(refs->d_lower_frag32);
+    if (refs->d_upper_frag32) (void)hipFree(refs->d_upper_frag32);
     delete refs;
     return RSR_OK;
 }

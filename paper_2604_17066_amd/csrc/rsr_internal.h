@@ -117,6 +117,11 @@ struct rsr_refs {
     float* d_lower_cinit4 = nullptr;      // [TL * 16]: -0.5 (row) or +0.5 (pad row)
     int8_t* d_upper_frag4 = nullptr;      // [TU][KS4][64][16]: t(r) as -1 nibbles
     float* d_upper_cinit4 = nullptr;      // [TU * 16]: |t(r)| - 0.5 (row) or +0.5 (pad row)
+    // FP4 form on 32-row tiles (k_dom_fp4x32): KS steps of 64 k; lane l of a
+    // step holds row l % 32, packed word 2 s + l / 32 as +1 nibbles (NOT
+    // t(r) for lower rows, t(r) for upper rows); ceil(R / 32) tiles per side.
+    int8_t* d_lower_frag32 = nullptr;     // [ceil(R_L/32)][KS][64][16]
+    int8_t* d_upper_frag32 = nullptr;     // [ceil(R_U/32)][KS][64][16]
 };
 
 struct rsr_system {
