@@ -86,8 +86,8 @@ def main():
         print(json.dumps({name: runs[name]() for name in args.only_legs.split(",")}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
-              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -61,7 +61,7 @@ typedef enum {
     RSR_EINVAL = 1,       /* an argument failed validation; nothing was launched */
     RSR_ENOMEM = 2,       /* a device or pinned-host allocation failed */
     RSR_EHIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
-    RSR_EUNSUPPORTED = 4  /* valid request outside this build's limits */
+    RSR_EUNSUPPORTED = 4  /* valid request outside the library's limits */
 } rsr_status;
 
 enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
@@ -70,7 +70,7 @@ enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown whic
 enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2, RSR_SYS_MAX_FLOW = 3,
        RSR_SYS_HOST_CALLBACK = 4 };  /* rsr_system_desc kind */
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define RSR_MAX_K 16
 #define RSR_MAX_BITS 4096   /* n * (K-1) */
 #define RSR_MAX_NODES 4096

@@ -11,7 +11,9 @@
 //     S samples against the round's rows of both sides, interleaved, and the
 //     wave leaves the round as soon as all its lanes have matched (vote every 8
 //     rows).  Matched samples get their flag; the others are copied (packed
-//     words and global index) to a compact buffer.
+//     words and global index) to a compact buffer.  With shape.mfma_head the
+//     round is one 32-row tile per side in the FP4 matrix-core form instead
+//     (k_casc_head.hip), which streams the samples at close to memory speed.
 //   later rounds: the undecided samples are few, so the round's rows are split
 //     into `chunks` contiguous ranges taken by different waves (k_casc_test,
 //     grid y = chunk) to keep the GPU busy; a chunk that finds a match ORs it
@@ -28,95 +30,17 @@
 // Compaction reserves output slots with one atomic per block for all of the
 // block's samples (wave ballots, an LDS prefix over the block's waves;
 // compact.h): the grid-wide counter's atomics are the contended part.
+#include "casc_popcount.h"
 #include "compact.h"
 
 namespace rsr {
 namespace {
 
+using namespace casc;
+
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxChunks = 64;
-
-// Rows per side staged in LDS at a time (at most 32 KB for both sides).
-template <int W>
-constexpr int tile_rows() {
-    return 4096 / W > 64 ? 64 : (4096 / W < 8 ? 8 : 4096 / W);
-}
-
-// Block-level: tests S samples per lane against rows [l0, l1) (lower) and
-// [u0, u1) (upper), interleaved.  The rows pass through LDS in tiles (one
-// coalesced cooperative load per tile; the reads are wave-uniform, so every
-// LDS access is a broadcast).  A wave stops testing once all its live lanes
-// have matched (vote every 8 rows); the block leaves when every wave has.
-// Every thread of the block must call it.
-template <int W, int S>
-__device__ __forceinline__ void test_rows(const uint32_t (&x)[S][W], const uint32_t (&nx)[S][W],
-                                          const bool (&live)[S], const uint32_t* __restrict__ low_n,
-                                          int l0, int l1, const uint32_t* __restrict__ up_b,
-                                          int u0, int u1, uint32_t (&mnL)[S],
-                                          uint32_t (&mnU)[S], uint32_t* lds) {
-    constexpr int T = tile_rows<W>();
-    const int nL = l1 - l0, nU = u1 - u0;
-    const int n_max = nL > nU ? nL : nU;
-    bool any_live = false;
-#pragma unroll
-    for (int s = 0; s < S; ++s) any_live = any_live || live[s];
-    bool wave_done = !__any(any_live);
-    const uint32_t* lo_src = low_n + static_cast<int64_t>(l0) * W;
-    const uint32_t* up_src = up_b + static_cast<int64_t>(u0) * W;
-    for (int t0 = 0; t0 < n_max; t0 += T) {
-        __syncthreads();
-        const int lo_words = (nL - t0 < T ? (nL - t0 > 0 ? nL - t0 : 0) : T) * W;
-        const int up_words = (nU - t0 < T ? (nU - t0 > 0 ? nU - t0 : 0) : T) * W;
-        for (int k = threadIdx.x; k < T * W; k += kBlock) {
-            lds[k] = k < lo_words ? lo_src[static_cast<int64_t>(t0) * W + k] : 0u;
-            lds[T * W + k] = k < up_words ? up_src[static_cast<int64_t>(t0) * W + k] : 0u;
-        }
-        __syncthreads();
-        if (!wave_done) {
-            const int cnt = n_max - t0 < T ? n_max - t0 : T;
-            for (int r0 = 0; r0 < cnt; r0 += 8) {
-#pragma unroll
-                for (int r = r0; r < r0 + 8; ++r) {
-                    if (t0 + r < nL) {
-                        const uint32_t* row = lds + r * W;
-                        uint32_t rw[W];
-#pragma unroll
-                        for (int w = 0; w < W; ++w) rw[w] = row[w];
-#pragma unroll
-                        for (int s = 0; s < S; ++s) {
-                            uint32_t t = 0;
-#pragma unroll
-                            for (int w = 0; w < W; ++w) t = (x[s][w] & rw[w]) | t;
-                            mnL[s] = min(mnL[s], t);
-                        }
-                    }
-                    if (t0 + r < nU) {
-                        const uint32_t* row = lds + T * W + r * W;
-                        uint32_t rw[W];
-#pragma unroll
-                        for (int w = 0; w < W; ++w) rw[w] = row[w];
-#pragma unroll
-                        for (int s = 0; s < S; ++s) {
-                            uint32_t t = 0;
-#pragma unroll
-                            for (int w = 0; w < W; ++w) t = (nx[s][w] & rw[w]) | t;
-                            mnU[s] = min(mnU[s], t);
-                        }
-                    }
-                }
-                bool done = true;
-#pragma unroll
-                for (int s = 0; s < S; ++s) done = done && (!live[s] || mnL[s] == 0u || mnU[s] == 0u);
-                if (__all(done)) {
-                    wave_done = true;
-                    break;
-                }
-            }
-        }
-        if (__syncthreads_and(wave_done ? 1 : 0)) break;
-    }
-}
 
 template <int W, int S>
 __global__ __launch_bounds__(kBlock) void k_casc_fused(
@@ -159,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
         uint32_t mnL[S], mnU[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
-        test_rows<W, S>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
+        test_rows<W, S, kBlock>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
         bool carry[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -217,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_test(
             nx[0][w] = ~x[0][w];
         }
         uint32_t mnL[1] = {0xFFFFFFFFu}, mnU[1] = {0xFFFFFFFFu};
-        test_rows<W, 1>(x, nx, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU, s_rows);
+        test_rows<W, 1, kBlock>(x, nx, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU, s_rows);
         const uint32_t bits = (mnL[0] == 0u ? 1u : 0u) | (mnU[0] == 0u ? 2u : 0u);
         if (live[0] && bits) atomicOr(&match[d], bits);
     }
@@ -292,10 +216,13 @@ hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
         hipError_t e;
         // With the matrix-core tail, an unsplit round after round 0 runs whole
         // in the FP4 form (test, flags and compaction in one kernel).  Round 0
-        // stays on the vector ALU: most samples stop within its first rows,
-        // which the popcount form's early exit exploits.
+        // runs in the FP4 32 x 32 form with shape.mfma_head (one tile per
+        // side, no early exit needed), else on the vector ALU with a per-wave
+        // early exit.
         const bool mfma_round = shape.mfma_tail && refs->KS4 > 0 && round > 0;
-        if (chunks == 1 && mfma_round) {
+        if (round == 0 && shape.mfma_head && shape.first == 32 && casc_head_supported(refs)) {
+            e = launch_casc_head(st, refs, seg, cb, last ? 1 : 0);
+        } else if (chunks == 1 && mfma_round) {
             e = launch_casc_mfma_round(st, refs, seg, csrc, cb.stride, src_idx, src_count, N, N,
                                        l0, l1, u0, u1, grid_cap, dst, dst_idx, dst_match,
                                        cb.stride, dst_count, last ? 1 : 0);

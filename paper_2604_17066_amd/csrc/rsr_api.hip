@@ -221,8 +221,17 @@ void fill_model_stage(const ModelLayout& L, int n, int K, const double* p, void*
     for (size_t i = 0; i < static_cast<size_t>(n) * K; ++i) pf[i] = static_cast<float>(p[i]);
 }
 
-rsr_status ensure_cascade(rsr_ctx* ctx, int W, int64_t N) {
+rsr_status ensure_cascade(rsr_ctx* ctx, int W, int64_t N, int64_t state_words = 0) {
     const int64_t words = 2 * static_cast<int64_t>(W) * N, idx = 4 * N;
+    if (ctx->ws.casc_state_cap < state_words) {
+        if (ctx->ws.casc_state) RSR_HIP(ctx, hipFree(ctx->ws.casc_state));
+        ctx->ws.casc_state = nullptr;
+        ctx->ws.casc_state_cap = 0;
+        // Rounded to whole u64 (the state is cleared 8 bytes at a time).
+        const int64_t cap = (state_words + 1) / 2 * 2;
+        RSR_HIP(ctx, rsr::dev_malloc(&ctx->ws.casc_state, sizeof(uint32_t) * static_cast<size_t>(cap)));
+        ctx->ws.casc_state_cap = cap;
+    }
     if (ctx->ws.casc_words_cap < words) {
         if (ctx->ws.casc_words) RSR_HIP(ctx, hipFree(ctx->ws.casc_words));
         ctx->ws.casc_words = nullptr;
@@ -290,7 +299,8 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
     ctx->arch = prop.gcnArchName;
     rsr_status st = RSR_OK;
     if (rsr::dev_malloc(&ctx->ws.counters, sizeof(uint64_t) * 16) != hipSuccess ||
-        rsr::dev_malloc(&ctx->ws.casc_counters, sizeof(uint64_t) * 16) != hipSuccess ||
+        rsr::dev_malloc(&ctx->ws.casc_counters,
+                        sizeof(uint64_t) * rsr::CascadeBuffers::kCounterU64) != hipSuccess ||
         rsr::dev_malloc(&ctx->ws.count_part, sizeof(uint64_t) * rsr::kMaxReduceBlocks * 8) != hipSuccess ||
         rsr::dev_malloc(&ctx->ws.grad_part, sizeof(uint32_t) * (static_cast<size_t>(RSR_MAX_BITS) + 1) *
                                                 rsr::kMaxGradBlocks) != hipSuccess ||
@@ -319,6 +329,7 @@ rsr_status rsr_ctx_destroy(rsr_ctx* ctx) {
     if (ctx->ws.casc_counters) (void)hipFree(ctx->ws.casc_counters);
     if (ctx->ws.casc_words) (void)hipFree(ctx->ws.casc_words);
     if (ctx->ws.casc_index) (void)hipFree(ctx->ws.casc_index);
+    if (ctx->ws.casc_state) (void)hipFree(ctx->ws.casc_state);
     if (ctx->ws.list) (void)hipFree(ctx->ws.list);
     if (ctx->ws.count_part) (void)hipFree(ctx->ws.count_part);
     if (ctx->ws.grad_part) (void)hipFree(ctx->ws.grad_part);
@@ -754,23 +765,42 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         form = RSR_MFMA_FP4;
     const bool matrix = form == RSR_MFMA || form == RSR_MFMA_FP4;
     if (mode == RSR_LABEL && !matrix && refs->consistent && N <= 0x7FFFFFFFll) {
-        rsr_status st = ensure_cascade(ctx, refs->W, N);
+        // The automatic form with matrix-core operands runs the rounds after
+        // round 0 in one persistent launch when the rows are many (its rounds
+        // then outnumber what the round kernels split well); otherwise, and
+        // for the popcount form, the round kernels.
+        const int64_t n_max = refs->R_L > refs->R_U ? refs->R_L : refs->R_U;
+        const bool persist = form == RSR_AUTO && refs->KS > 0 && n_max >= rsr::kPersistRows;
+        const int64_t stride = persist ? rsr::casc_persist_stride(refs, N, ctx->cu_count) : N;
+        const int64_t state_words = persist ? rsr::casc_persist_state_words(stride, refs->KS) : 0;
+        rsr_status st = ensure_cascade(ctx, refs->W, stride, state_words);
         if (st != RSR_OK) return st;
         rsr::CascadeBuffers cb;
         cb.words[0] = ctx->ws.casc_words;
-        cb.words[1] = ctx->ws.casc_words + static_cast<int64_t>(refs->W) * N;
+        cb.words[1] = ctx->ws.casc_words + static_cast<int64_t>(refs->W) * stride;
         cb.index[0] = ctx->ws.casc_index;
-        cb.index[1] = ctx->ws.casc_index + N;
-        cb.match[0] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 2 * N);
-        cb.match[1] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 3 * N);
-        cb.stride = N;
+        cb.index[1] = ctx->ws.casc_index + stride;
+        cb.match[0] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 2 * stride);
+        cb.match[1] = reinterpret_cast<uint32_t*>(ctx->ws.casc_index + 3 * stride);
+        cb.stride = stride;
         cb.counters = ctx->ws.casc_counters;
+        cb.regions = reinterpret_cast<uint32_t*>(ctx->ws.casc_counters + 16);
         // The automatic form runs the rounds after round 0 in the FP4
         // matrix-core form when the handle has its operands; the popcount
         // form stays popcount.
         const rsr::CascadeShape shape = form == RSR_AUTO && refs->KS4 > 0
                                             ? rsr::mfma_tail_shape()
                                             : rsr::CascadeShape{};
+        if (persist) {
+            RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, reinterpret_cast<uint64_t*>(ctx->ws.casc_state),
+                                              (state_words + 1) / 2, 0));
+            RSR_HIP(ctx, rsr::launch_casc_persist(ctx->stream, refs,
+                                                  rsr::single_src(d_samples, N, d_flags, nullptr), cb,
+                                                  rsr::mfma_head_shape(), ctx->ws.casc_state,
+                                                  reinterpret_cast<unsigned long long*>(ctx->ws.counters + 14),
+                                                  ctx->cu_count));
+            return RSR_OK;
+        }
         RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0));
         RSR_HIP(ctx, rsr::launch_dom_cascade(ctx->stream, refs,
                                              rsr::single_src(d_samples, N, d_flags, nullptr), cb,
@@ -847,10 +877,16 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
     else
         RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
                                         ctx->ws.count_part));
-    RSR_HIP(ctx, hipMemcpyAsync(ctx->ws.host_counts, ctx->ws.counters, sizeof(uint64_t) * 5,
+    RSR_HIP(ctx, hipMemcpyAsync(ctx->ws.host_counts, ctx->ws.counters, sizeof(uint64_t) * 16,
                                 hipMemcpyDeviceToHost, ctx->stream));
     RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const uint64_t* c = ctx->ws.host_counts;
+    if (c[14] != 0) {
+        // A persistent cascade since the last check could not synchronise its
+        // blocks in time: its flags are not to be trusted.
+        RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, ctx->ws.counters + 14, 1, 0));
+        return fail(ctx, RSR_EHIP, "a persistent classification timed out at a grid barrier");
+    }
     out->n_L = c[0];
     out->n_U = c[1];
     out->n_u = c[2];

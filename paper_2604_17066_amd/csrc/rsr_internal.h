@@ -63,6 +63,8 @@ struct Workspace {
     uint32_t* casc_words = nullptr;    // 2 x [W][N] u32 (cascade)
     int32_t* casc_index = nullptr;     // 2 x [N] i32 indices, then 2 x [N] u32 match words
     int64_t casc_words_cap = 0, casc_index_cap = 0;
+    uint32_t* casc_state = nullptr;    // persistent cascade state (counts, items, barrier, tickets)
+    int64_t casc_state_cap = 0;        // in u32 words
     CallbackStage cb;
 };
 
@@ -213,11 +215,17 @@ __device__ __forceinline__ uint8_t* seg_Y(const SegSrc& s, int j) {
 // sample words [W][N] and original indices [N], plus one counter per round.
 struct CascadeBuffers {
     static constexpr int kMaxRounds = 12;
+    // Most output regions of the matrix-core round 0 (one per block).
+    static constexpr int kMaxRegions = 2048;
+    // u64 words of the counters allocation: 16 round counters, then
+    // kMaxRegions u32 region counts.
+    static constexpr int kCounterU64 = 16 + kMaxRegions / 2;
     uint32_t* words[2] = {nullptr, nullptr};  // [W][stride] each
     int32_t* index[2] = {nullptr, nullptr};   // [stride] each
     uint32_t* match[2] = {nullptr, nullptr};  // [stride] each: match bits of split rounds
     int64_t stride = 0;                       // capacity in samples (>= total)
     uint64_t* counters = nullptr;  // [kMaxRounds], zeroed before the first round
+    uint32_t* regions = nullptr;   // [kMaxRegions] (k_casc_head)
 };
 
 // Round boundaries of the cascade: rows [0, first), [first, first*growth), ...
@@ -229,6 +237,9 @@ struct CascadeShape {
     int split_rows = 128;
     // Rounds after round 0 in the FP4 matrix-core form (needs refs->KS4 > 0).
     bool mfma_tail = false;
+    // Round 0 in the FP4 32 x 32 form (k_casc_head) when first == 32 and
+    // casc_head_supported(refs); otherwise on the vector ALU.
+    bool mfma_head = false;
 };
 
 // Default shape with the matrix-core tail (measured on graph2: matrix-core
@@ -241,6 +252,27 @@ inline CascadeShape mfma_tail_shape() {
     s.mfma_tail = true;
     return s;
 }
+
+// Default shape with every round in the matrix-core form: round 0 is one
+// 32-row tile per side.
+inline CascadeShape mfma_head_shape() {
+    CascadeShape s;
+    s.first = 32;
+    s.growth = 6;
+    s.split_rows = 256;
+    s.mfma_tail = true;
+    s.mfma_head = true;
+    return s;
+}
+
+// Rows per side from which the automatic LABEL form runs the persistent
+// cascade instead of the round kernels (measured on MI355X: 0.32 against
+// 0.44 ms at 2.5e4 rows of 590 bits, 0.22 against 0.16 ms at 1e4 rows of 295
+// bits, N = 1e6).
+constexpr int64_t kPersistRows = 16384;
+
+// Largest refs->KS (64-wide k-steps) of the matrix-core round 0.
+constexpr int kMaxHeadSteps = 10;
 
 // Kernel launchers (each returns the hipError_t of the launch).
 hipError_t launch_sample(hipStream_t st, const rsr_model* m, uint64_t seed, uint32_t stream_id,
@@ -266,6 +298,25 @@ hipError_t launch_casc_mfma(hipStream_t st, const rsr_refs* refs, const uint32_t
                             int64_t cstride, const unsigned long long* src_count, int64_t max_count,
                             int l0, int l1, int u0, int u1, int chunks, int grid_cap,
                             uint32_t* match);
+// The persistent LABEL cascade (k_cascade_persist.hip): a popcount round-0
+// launch, then the FP4 32 x 32 rounds in one cooperative launch.  cb.stride
+// is at least casc_persist_stride(refs, seg.total, cus); d_state holds
+// casc_persist_state_words(cb.stride, refs->KS) u32, zero on entry (left
+// nonzero); *d_err becomes 1 if a grid barrier timed out.
+hipError_t launch_casc_persist(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                               const CascadeBuffers& cb, const CascadeShape& shape,
+                               unsigned* d_state, unsigned long long* d_err, int cus);
+int64_t casc_persist_state_words(int64_t stride, int KS);
+// Compact-buffer capacity (cb.stride) the persistent cascade needs for N
+// samples: N plus the slack of its per-block output regions.
+int64_t casc_persist_stride(const rsr_refs* refs, int64_t N, int cus);
+// Round 0 of the cascade in the FP4 32 x 32 form (k_casc_head.hip): rows
+// [0, 32) of both sides over all samples of seg; flags the decided samples
+// (all samples when last) and packs the others into cb.words[0] / index[0] /
+// match[0], their number in cb.counters[0] (through regions of cb.words[1]).
+bool casc_head_supported(const rsr_refs* refs);
+hipError_t launch_casc_head(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
+                            const CascadeBuffers& cb, int last);
 hipError_t launch_label(hipStream_t st, const SegSrc& seg, int32_t* d_list, uint64_t* d_counter,
                         int grid_cap);
 hipError_t launch_bfs(hipStream_t st, const rsr_system* sys, const SegSrc& seg,

@@ -54,7 +54,8 @@ struct TuneEntry {
 
 // The tuning cache file is one JSON object: keys are segment-shape strings,
 // values are objects of numbers {"choice", "first", "growth", "split", "tail",
-// "ms"}.  This reader accepts exactly that (strings without escapes) and
+// "ms"} ("tail": 0 popcount rounds, 1 matrix-core rounds after round 0, 2
+// matrix-core rounds from round 0 on).  This reader accepts exactly that (strings without escapes) and
 // returns false on anything else.
 class CacheReader {
   public:
@@ -218,6 +219,7 @@ rsr::CascadeBuffers casc_buffers(const rsr_plan* p) {
     cb.match[1] = reinterpret_cast<uint32_t*>(p->d_casc_index + 3 * p->casc_cap);
     cb.stride = p->casc_cap;
     cb.counters = p->d_casc_counters;
+    cb.regions = reinterpret_cast<uint32_t*>(p->d_casc_counters + 16);
     return cb;
 }
 
@@ -287,7 +289,9 @@ std::string segment_key(const rsr_ctx* ctx, const Segment& s) {
 
 bool choice_runs(const Segment& s) {
     switch (s.choice) {
-        case kCascade: return s.refs->consistent && (!s.shape.mfma_tail || s.refs->KS4 > 0);
+        case kCascade:
+            return s.refs->consistent && (!s.shape.mfma_tail || s.refs->KS4 > 0) &&
+                   (!s.shape.mfma_head || rsr::casc_head_supported(s.refs));
         case kBitsPerJob: return true;
         case kMfmaPerJob: return s.refs->KS > 0;
         case kMfma4PerJob: return s.refs->KS4 > 0;
@@ -357,15 +361,19 @@ rsr_status tune_segment(rsr_plan* p, int si) {
     if (s.refs->consistent) {
         std::vector<Cand> forms = {{kCascade, rsr::CascadeShape{}}};
         if (s.refs->KS4 > 0) forms.push_back({kCascade, rsr::mfma_tail_shape()});
+        if (s.refs->KS4 > 0 && rsr::casc_head_supported(s.refs))
+            forms.push_back({kCascade, rsr::mfma_head_shape()});
         st = trial(forms);
-        const bool tail = s.shape.mfma_tail;
+        const bool tail = s.shape.mfma_tail, head = s.shape.mfma_head;
         std::vector<Cand> shapes;
-        const int firsts[] = {8, 16, 32, 64};
+        // The matrix-core round 0 is one 32-row tile per side.
+        const std::vector<int> firsts = head ? std::vector<int>{32} : std::vector<int>{8, 16, 32, 64};
         const int growths[] = {4, 8};
         const int splits[] = {64, 256};
         for (int f : firsts)
             for (int g : growths)
-                for (int sp : splits) shapes.push_back({kCascade, rsr::CascadeShape{f, g, sp, tail}});
+                for (int sp : splits)
+                    shapes.push_back({kCascade, rsr::CascadeShape{f, g, sp, tail, head}});
         if (st == RSR_OK) st = trial(shapes);
     } else {
         std::vector<Cand> forms = {{kBitsPerJob, rsr::CascadeShape{}}};
@@ -527,7 +535,8 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
     dmalloc(reinterpret_cast<void**>(&p->d_casc_words),
             sizeof(uint32_t) * 2 * static_cast<size_t>(max_words) * max_total);
     dmalloc(reinterpret_cast<void**>(&p->d_casc_index), sizeof(int32_t) * 4 * max_total);
-    dmalloc(reinterpret_cast<void**>(&p->d_casc_counters), sizeof(uint64_t) * 16);
+    dmalloc(reinterpret_cast<void**>(&p->d_casc_counters),
+            sizeof(uint64_t) * rsr::CascadeBuffers::kCounterU64);
     dmalloc(reinterpret_cast<void**>(&p->d_list), sizeof(int32_t) * max_total);
     dmalloc(reinterpret_cast<void**>(&p->d_list_counter), sizeof(uint64_t) * 2);
     dmalloc(reinterpret_cast<void**>(&p->d_G_all), sizeof(float) * p->G_total);
@@ -562,7 +571,7 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             if (it != cache.end()) {
                 const TuneEntry& te = it->second;
                 sg.choice = static_cast<Choice>(te.choice);
-                sg.shape = rsr::CascadeShape{te.first, te.growth, te.split, te.tail != 0};
+                sg.shape = rsr::CascadeShape{te.first, te.growth, te.split, te.tail != 0, te.tail == 2};
                 sg.tuned_ms = static_cast<float>(te.ms);
                 // A stored choice the handle cannot run (no matrix-core
                 // operands, or a cascade on inconsistent rows) is retimed.
@@ -578,7 +587,7 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             te.first = sg.shape.first;
             te.growth = sg.shape.growth;
             te.split = sg.shape.split_rows;
-            te.tail = sg.shape.mfma_tail ? 1 : 0;
+            te.tail = sg.shape.mfma_head ? 2 : (sg.shape.mfma_tail ? 1 : 0);
             te.ms = sg.tuned_ms;
             cache[key] = te;
             added = true;

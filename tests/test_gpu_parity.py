@@ -372,6 +372,31 @@ def test_cascade_fp4_split_rounds_large_rows(rsr_ctx):
     np.testing.assert_array_equal(auto, want)
 
 
+def test_persistent_cascade_long_rows(rsr_ctx):
+    """2.2e4 path and cut rows of the 647-edge graph (21 words per row): the
+    automatic LABEL form runs the persistent cascade (round 0 on the vector
+    ALU, the later rounds in one cooperative launch, compacted through
+    per-block regions).  A ragged N; labels equal the oracle's and the
+    popcount cascade's, and a second call on the same buffers repeats them."""
+    cfg = WL.configs.batched(n_scen=1, N=1, graphs=[5], ref_scale=1.0)
+    sys_ = cfg["systems"][0]
+    n = sys_["n"]
+    p = cfg["jobs"][0]["p"]
+    N = 6007
+    m, xs = _sample(rsr_ctx, p, 5, 0, 0, N)
+    refs = R.Refs(rsr_ctx, n, 2, sys_["lower"], sys_["upper"])
+    assert refs.consistent and max(refs.R_L, refs.R_U) >= 16_384
+    auto = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO)
+    first = _np(auto).copy()
+    R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO, flags=auto)
+    pop = _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT))
+    x = oracle.sample(p, 5, 0, 0, N)
+    want, _, _ = oracle.classify(sys_["lower"], sys_["upper"], x, mode=0)
+    np.testing.assert_array_equal(first, want)
+    np.testing.assert_array_equal(_np(auto), want)
+    np.testing.assert_array_equal(pop, want)
+
+
 @pytest.mark.parametrize("form,per_cu", [(R.RSR_MFMA, 640), (R.RSR_MFMA, 512),
                                          (R.RSR_MFMA_FP4, 1024), (R.RSR_MFMA_FP4, 512)])
 def test_classify_both_sample_tile_counts(rsr_ctx, form, per_cu):
