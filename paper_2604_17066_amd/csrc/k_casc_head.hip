@@ -38,7 +38,8 @@ __global__ __launch_bounds__(kBlock) void k_casc_head(SegSrc seg, int n, int PW,
                                                       uint32_t* __restrict__ region_cnt, int last) {
     constexpr int G = 32 * MT;
     __shared__ unsigned s_out;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // The wave index is uniform (readfirstlane: scalar loop and branches).
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = lane & 31, half = lane >> 5;
     const uint32_t below = (1u << col) - 1u;
     const int64_t begin = static_cast<int64_t>(blockIdx.x) * span;
@@ -53,10 +54,30 @@ __global__ __launch_bounds__(kBlock) void k_casc_head(SegSrc seg, int n, int PW,
         vm[s] = expand_word_fp4(valid_word(2 * s + half, n, PW, W));
     }
     const v16f start = v16f{} - 0.5f;
+    // Words of the step at b0, read unconditionally from clamped addresses
+    // (a sample past the end reads the block's last sample and is zeroed).
+    auto load_step = [&](int64_t b0, uint32_t (&raw)[MT][KS]) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            const int64_t g = b0 + 32 * t + col;
+            const int64_t gc = g < end ? g : end - 1;
+            int job;
+            int64_t at, stride;
+            seg_locate(seg, gc, job, at);
+            const uint32_t* base = seg_words(seg, job, stride);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int w = 2 * s + half;
+                const uint32_t v = base[(w < W ? w : W - 1) * stride + at];
+                raw[t][s] = (g < end && w < W) ? v : 0u;
+            }
+        }
+    };
+    const int64_t step = static_cast<int64_t>(kWaves) * G;
     // Wave-level loop: no block synchronisation until the end.
-    for (int64_t b0 = begin + static_cast<int64_t>(wave) * G; b0 < end;
-         b0 += static_cast<int64_t>(kWaves) * G) {
-        uint32_t raw[MT][KS];
+    for (int64_t b0 = begin + static_cast<int64_t>(wave) * G; b0 < end; b0 += step) {
+        uint32_t cur[MT][KS];
+        load_step(b0, cur);
         v4i bf[MT][KS];
         bool valid[MT];
         int64_t g[MT];
@@ -64,19 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_casc_head(SegSrc seg, int n, int PW,
         for (int t = 0; t < MT; ++t) {
             g[t] = b0 + 32 * t + col;
             valid[t] = g[t] < end;
-            int job = 0;
-            int64_t at = 0, stride = 0;
-            const uint32_t* base = nullptr;
-            if (valid[t]) {
-                seg_locate(seg, g[t], job, at);
-                base = seg_words(seg, job, stride);
-            }
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const int w = 2 * s + half;
-                raw[t][s] = (valid[t] && w < W) ? base[w * stride + at] : 0u;
-                bf[t][s] = expand_word_fp4(raw[t][s]);
-            }
+            for (int s = 0; s < KS; ++s) bf[t][s] = expand_word_fp4(cur[t][s]);
         }
         bool lowered[MT], raised[MT];
         bool any_left = false;
@@ -91,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_head(SegSrc seg, int n, int PW,
                 v16f r = start;
 #pragma unroll
                 for (int s = 0; s < KS; ++s) r = mfma32_step(aL[s], bf[t][s], r);
-                const int m = fold32_last<false>(r, 0, rl, half);
+                const int m = rl >= 32 ? fold32<false>(r, 0) : fold32_last<false>(r, 0, rl, half);
                 lowered[t] = min(m, __shfl_xor(m, 32)) < 0;
             }
         }
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_head(SegSrc seg, int n, int PW,
                 v16f r = start;
 #pragma unroll
                 for (int s = 0; s < KS; ++s) r = mfma32_step(aU[s], bf[t][s] ^ vm[s], r);
-                const int m = fold32_last<false>(r, 0, ru, half);
+                const int m = ru >= 32 ? fold32<false>(r, 0) : fold32_last<false>(r, 0, ru, half);
                 raised[t] = min(m, __shfl_xor(m, 32)) < 0;
             }
         }
@@ -134,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_head(SegSrc seg, int n, int PW,
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                     const int w = 2 * s + half;
-                    if (w < W) dst[w * dst_stride + o] = raw[t][s];
+                    if (w < W) dst[w * dst_stride + o] = cur[t][s];
                 }
             }
         }

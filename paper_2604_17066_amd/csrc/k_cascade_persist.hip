@@ -39,8 +39,8 @@ namespace {
 using namespace mf;
 using namespace casc;
 
-#ifndef RSR_CASC_MT
-#define RSR_CASC_MT 2
+#ifndef RSR_CASC_MT2_KS
+#define RSR_CASC_MT2_KS 10
 #endif
 #ifndef RSR_CASC_RING
 #define RSR_CASC_RING 2
@@ -62,7 +62,7 @@ constexpr int kBarGroups = 64;
 constexpr int kLine = 32;
 
 // Sample tiles (32 samples) per wave in the matrix-core rounds.
-constexpr int casc_tiles32(int KS) { return KS <= 10 ? RSR_CASC_MT : 1; }
+constexpr int casc_tiles32(int KS) { return KS <= RSR_CASC_MT2_KS ? 2 : 1; }
 
 // Samples per lane in round 0.
 constexpr int r0_samples(int W) { return W <= 12 ? 4 : (W <= 24 ? 2 : 1); }
@@ -290,39 +290,36 @@ __device__ __forceinline__ int64_t region_slot(const uint32_t* prefix, int nreg,
 // One wave's pass over a range of 32-row tiles of one side (rows past `rows`
 // from the range's first tile are padding).  The tiles' A fragments are read
 // straight from memory into a ring of R register sets, R - 1 tiles ahead of
-// the products.  acc[t] keeps the signed minimum over this lane's rows
-// (negative = some row matched).  The wave leaves once every live sample is
-// decided.
+// the products.  The read-ahead is unconditional (past the last tile it
+// reads the last tile again): a conditional load would make the compiler's
+// wait counts cover both paths, i.e. wait for the tile just requested.
+// acc[t] keeps the signed minimum over this lane's rows (negative = some row
+// matched).  The wave leaves once every live sample is decided.
 template <int KS, int MT, int R>
 __device__ __forceinline__ void wave_pass(const v4i (&bf)[MT][KS], const v4i* __restrict__ frag,
                                           int64_t rows, int (&acc)[MT], const bool (&live)[MT]) {
     if (rows <= 0) return;
     const int lane = threadIdx.x & 63, half = lane >> 5;
-    const int tiles = static_cast<int>((rows + 31) / 32);
+    const int tiles = __builtin_amdgcn_readfirstlane(static_cast<int>((rows + 31) / 32));
     const int last_rows = static_cast<int>(rows - 32 * static_cast<int64_t>(tiles - 1));
     const v16f start = v16f{} - 0.5f;
     v4i ring[R][KS];
 #pragma unroll
-    for (int k = 0; k < R - 1; ++k)
-        if (k < tiles) {
+    for (int k = 0; k < R - 1; ++k) {
+        const int64_t tk = k < tiles ? k : tiles - 1;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) ring[k][s] = frag[(static_cast<int64_t>(k) * KS + s) * 64 + lane];
-        }
+        for (int s = 0; s < KS; ++s) ring[k][s] = frag[(tk * KS + s) * 64 + lane];
+    }
     bool stop = false;
     for (int t0 = 0; !stop; t0 += R) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int t = t0 + k;
-            if (stop || t >= tiles) {
-                stop = true;
-                break;
-            }
-            const int tn = t + R - 1;
-            if (tn < tiles) {
+            if (stop) break;
+            const int64_t tn = t + R - 1 < tiles ? t + R - 1 : tiles - 1;
 #pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    ring[(k + R - 1) % R][s] = frag[(static_cast<int64_t>(tn) * KS + s) * 64 + lane];
-            }
+            for (int s = 0; s < KS; ++s)
+                ring[(k + R - 1) % R][s] = frag[(tn * KS + s) * 64 + lane];
             const bool more = t + 1 < tiles;
             v16f r[MT];
 #pragma unroll
@@ -349,10 +346,12 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
     __shared__ uint32_t s_prefix[kMaxRegions + 1];
     __shared__ uint32_t s_wave[kWaves];
     __shared__ unsigned s_out;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // The wave index is uniform: readfirstlane lets the item loop and its
+    // branches run on the scalar unit.
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t gwave = static_cast<int64_t>(blockIdx.x) * kWaves + wave;
     const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWaves;
-    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t below32 = (1ull << (lane & 31)) - 1ull;
     uint32_t* st = a.state;
     for (int r = 1; r < a.rounds; ++r) {
         const bool last = r + 1 == a.rounds;
@@ -410,7 +409,36 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
         // Output regions: a wave item compacts at most one group of G.
         const int64_t out_cap = static_cast<int64_t>(kWaves) * ((items + nwaves - 1) / nwaves) * G;
         const int64_t out_base = static_cast<int64_t>(blockIdx.x) * out_cap;
+        // An item's samples: lane l holds virtual positions gbase + 32 t +
+        // l % 32 and their words 2 s + l / 32, with the sample's index (read
+        // unconditionally from clamped positions: see wave_pass).  A second
+        // item read ahead does not help: loads complete in issue order, so
+        // the first tile's wait would cover it too.
+        struct Held {
+            uint32_t raw[MT][KS];
+            int64_t slot[MT];
+            int32_t idx[MT];
+            bool valid[MT];
+        };
+        auto fetch = [&](int64_t item, Held& h) {
+            const int64_t gbase = (item / chunks) * G;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const int64_t p = gbase + 32 * t + (lane & 31);
+                h.valid[t] = p < n_in;
+                h.slot[t] = region_slot(s_prefix, nreg, in_cap, p < n_in ? p : n_in - 1);
+                h.idx[t] = src_i[h.slot[t]];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int w = 2 * s + (lane >> 5);
+                    const uint32_t v = src_w[(w < a.W ? w : a.W - 1) * a.stride + h.slot[t]];
+                    h.raw[t][s] = (h.valid[t] && w < a.W) ? v : 0u;
+                }
+            }
+        };
         for (int64_t item = gwave; item < items; item += nwaves) {
+            Held cur;
+            fetch(item, cur);
             const int64_t g = item / chunks, c = item % chunks;
             const int cl0 = lt0 + static_cast<int>((TLr * c) / chunks);
             const int cl1 = lt0 + static_cast<int>((TLr * (c + 1)) / chunks);
@@ -418,34 +446,21 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
             const int cu1 = ut0 + static_cast<int>((TUr * (c + 1)) / chunks);
             const int64_t rl = cl1 > cl0 ? (32ll * cl1 < a.R_L ? 32ll * cl1 : a.R_L) - 32ll * cl0 : 0;
             const int64_t ru = cu1 > cu0 ? (32ll * cu1 < a.R_U ? 32ll * cu1 : a.R_U) - 32ll * cu0 : 0;
-            const int64_t gbase = g * G;
-            // This lane's samples: virtual positions gbase + 32 t + lane % 32,
-            // words 2 s + lane / 32.
-            int64_t slot[MT];
-            bool valid[MT];
             v4i bf[MT][KS];
 #pragma unroll
-            for (int t = 0; t < MT; ++t) {
-                const int64_t p = gbase + 32 * t + (lane & 31);
-                valid[t] = p < n_in;
-                slot[t] = valid[t] ? region_slot(s_prefix, nreg, in_cap, p) : 0;
+            for (int t = 0; t < MT; ++t)
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int w = 2 * s + (lane >> 5);
-                    const uint32_t bits = (valid[t] && w < a.W) ? src_w[w * a.stride + slot[t]] : 0u;
-                    bf[t][s] = expand_word_fp4(bits);
-                }
-            }
+                for (int s = 0; s < KS; ++s) bf[t][s] = expand_word_fp4(cur.raw[t][s]);
             int accL[MT], accU[MT];
             bool lowered[MT], todo[MT];
 #pragma unroll
             for (int t = 0; t < MT; ++t) accL[t] = accU[t] = 0;
-            wave_pass<KS, MT, RING>(bf, a.low32 + static_cast<int64_t>(cl0) * KS * 64, rl, accL, valid);
+            wave_pass<KS, MT, RING>(bf, a.low32 + static_cast<int64_t>(cl0) * KS * 64, rl, accL, cur.valid);
             bool any_left = false;
 #pragma unroll
             for (int t = 0; t < MT; ++t) {
                 lowered[t] = min(accL[t], __shfl_xor(accL[t], 32)) < 0;
-                todo[t] = valid[t] && !lowered[t];
+                todo[t] = cur.valid[t] && !lowered[t];
                 any_left = any_left || todo[t];
             }
             if (__any(any_left)) {
@@ -463,6 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
                 const int m = min(accU[t], __shfl_xor(accU[t], 32));
                 bits[t] = lowered[t] ? 1u : (m < 0 ? 2u : 0u);
             }
+            bool resolve = true;
             if (chunks > 1) {
                 // The match words are only touched by device-scope atomics
                 // until the group is resolved, which act at the device's
@@ -473,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
                 if (lane < 32) {
 #pragma unroll
                     for (int t = 0; t < MT; ++t)
-                        if (valid[t] && bits[t])
-                            dep |= __hip_atomic_fetch_or(&src_m[slot[t]], bits[t], __ATOMIC_RELAXED,
+                        if (cur.valid[t] && bits[t])
+                            dep |= __hip_atomic_fetch_or(&src_m[cur.slot[t]], bits[t], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                 }
                 asm volatile("" ::"v"(dep) : "memory");
@@ -486,40 +502,48 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
                     fin = ticket + 1 == static_cast<unsigned>(chunks) ? 1u : 0u;
                     if (fin) __hip_atomic_store(ticket_p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                if (!__shfl(fin, 0)) continue;
+                resolve = __shfl(fin, 0) != 0u;
+                if (resolve) {
 #pragma unroll
-                for (int t = 0; t < MT; ++t)
-                    bits[t] = valid[t] ? __hip_atomic_load(&src_m[slot[t]], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : 0u;
-            }
-            // Flags of the group's decided samples (all of them in the last
-            // round) and compaction of the others into this block's region:
-            // lanes 0..31 own the samples.
-#pragma unroll
-            for (int t = 0; t < MT; ++t) {
-                const bool own = lane < 32 && valid[t];
-                const uint32_t b = own ? bits[t] : 0u;
-                const int64_t gi = own ? static_cast<int64_t>(src_i[slot[t]]) : 0;
-                if (own && (b || last)) {
-                    int job;
-                    int64_t h;
-                    seg_locate(a.seg, gi, job, h);
-                    seg_flags(a.seg, job)[h] = static_cast<uint8_t>((b & 1u) ? 1 : ((b & 2u) ? 2 : 0));
+                    for (int t = 0; t < MT; ++t)
+                        bits[t] = cur.valid[t] ? __hip_atomic_load(&src_m[cur.slot[t]], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT)
+                                               : 0u;
                 }
-                if (last) continue;
-                const bool carry = own && b == 0u;
-                const uint64_t mask = __ballot(carry);
-                if (mask == 0) continue;
-                unsigned base = 0;
-                if (lane == 0) base = atomicAdd(&s_out, static_cast<unsigned>(__popcll(mask)));
-                base = __shfl(base, 0);
-                if (carry) {
-                    const int64_t o = out_base + base + __popcll(mask & below);
-                    a.index[out][o] = static_cast<int32_t>(gi);
-                    a.match[out][o] = 0u;
-                    for (int w = 0; w < a.W; ++w)
-                        a.words[out][w * a.stride + o] = src_w[w * a.stride + slot[t]];
+            }
+            if (resolve) {
+                // Flags of the group's decided samples (all of them in the
+                // last round; lanes 0..31) and compaction of the others into
+                // this block's region from the held words: lanes l and l + 32
+                // write the words 2 s and 2 s + 1 of their sample.
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    const uint32_t b = cur.valid[t] ? bits[t] : 0u;
+                    if (lane < 32 && cur.valid[t] && (b || last)) {
+                        int job;
+                        int64_t h;
+                        seg_locate(a.seg, cur.idx[t], job, h);
+                        seg_flags(a.seg, job)[h] = static_cast<uint8_t>((b & 1u) ? 1 : ((b & 2u) ? 2 : 0));
+                    }
+                    if (last) continue;
+                    const bool carry = cur.valid[t] && b == 0u;
+                    const uint64_t mask = __ballot(carry && lane < 32);
+                    if (mask == 0) continue;
+                    unsigned base = 0;
+                    if (lane == 0) base = atomicAdd(&s_out, static_cast<unsigned>(__popcll(mask)));
+                    base = __shfl(base, 0);
+                    if (carry) {
+                        const int64_t o = out_base + base + __popcll(mask & below32);
+                        if (lane < 32) {
+                            a.index[out][o] = cur.idx[t];
+                            a.match[out][o] = 0u;
+                        }
+#pragma unroll
+                        for (int s = 0; s < KS; ++s) {
+                            const int w = 2 * s + (lane >> 5);
+                            if (w < a.W) a.words[out][w * a.stride + o] = cur.raw[t][s];
+                        }
+                    }
                 }
             }
         }
