@@ -33,12 +33,12 @@ MFMA_I8_PEAK_OPS = 5.0e15
 MFMA_FP4_PEAK_FLOPS = 10.1e15
 # HBM bytes per launch of the COUNT-mode classification on the graph2 workload,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
-# (profiles/bench_graph2_hbm_traffic.md).  Set an entry to None when its kernel
+# (profiles/classify_hbm_traffic.md).  Set an entry to None when its kernel
 # changes, until the counters are taken again.
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
     "mfma": (433.88 + 0.95) * 2 ** 20,
-    "mfma_fp4": None,
+    "mfma_fp4": (107.20 + 0.95) * 2 ** 20,
 }
 
 
