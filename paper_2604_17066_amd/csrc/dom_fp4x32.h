@@ -259,16 +259,25 @@ __device__ __forceinline__ void load_samples32(const uint32_t* __restrict__ xs, 
                                                int64_t count, int W, int64_t wbase, int lane,
                                                v4i (&bf)[MT][KS], bool (&valid)[MT]) {
     const int col = lane & 31, half = lane >> 5;
+    // Reads from clamped positions, all issued before any is used (reads
+    // behind a condition make the wait counts cover every path).
+    uint32_t raw[MT][KS];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
         const int64_t h = wbase + 32 * t + col;
-        valid[t] = h < count;
+        const int64_t hc = h < count ? h : count - 1;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int w = 2 * s + half;
-            const uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * stride + h] : 0u;
-            bf[t][s] = expand_word_fp4(bits);
+            raw[t][s] = xs[static_cast<int64_t>(w < W ? w : W - 1) * stride + hc];
         }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        valid[t] = wbase + 32 * t + col < count;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            bf[t][s] = expand_word_fp4((valid[t] && 2 * s + half < W) ? raw[t][s] : 0u);
     }
 }
 

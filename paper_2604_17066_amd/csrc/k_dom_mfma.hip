@@ -280,23 +280,39 @@ __device__ __forceinline__ void load_samples(const uint32_t* __restrict__ xs, in
                                              int64_t count, int W, int64_t wbase, int col, int grp,
                                              const uint32_t* __restrict__ done, v4i (&bf)[MT][KS],
                                              bool (&valid)[MT]) {
+    // Every read is issued before any is used, from clamped positions (a
+    // position past the end reads the last sample and is masked below): reads
+    // behind a condition, or a word read that waits for the match word, would
+    // each cost a memory round trip of their own.
+    uint32_t raw[MT][KS], skip[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
         const int64_t h = wbase + 16 * t + col;
-        valid[t] = h < count && (!done || done[h] == 0u);
+        const int64_t hc = h < count ? h : count - 1;
+        skip[t] = done ? done[hc] : 0u;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int w = FP4 ? 4 * s + grp : 2 * s + (grp >> 1);
+            raw[t][s] = xs[static_cast<int64_t>(w < W ? w : W - 1) * stride + hc];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int64_t h = wbase + 16 * t + col;
+        valid[t] = h < count && skip[t] == 0u;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             v4i f;
             if constexpr (FP4) {
                 const int w = 4 * s + grp;
-                const uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * stride + h] : 0u;
+                const uint32_t bits = (valid[t] && w < W) ? raw[t][s] : 0u;
                 f.x = expand8_fp4(bits & 0xFFu);
                 f.y = expand8_fp4((bits >> 8) & 0xFFu);
                 f.z = expand8_fp4((bits >> 16) & 0xFFu);
                 f.w = expand8_fp4(bits >> 24);
             } else {
                 const int w = 2 * s + (grp >> 1);
-                uint32_t bits = (valid[t] && w < W) ? xs[static_cast<int64_t>(w) * stride + h] : 0u;
+                uint32_t bits = (valid[t] && w < W) ? raw[t][s] : 0u;
                 bits = (bits >> (16 * (grp & 1))) & 0xFFFFu;
                 f.x = expand4(bits & 0xFu);
                 f.y = expand4((bits >> 4) & 0xFu);
