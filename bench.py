@@ -38,7 +38,7 @@ MFMA_FP4_PEAK_FLOPS = 10.1e15
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
     "mfma": (433.88 + 0.95) * 2 ** 20,
-    "mfma_fp4": (107.20 + 0.95) * 2 ** 20,
+    "mfma_fp4": (63.40 + 0.95) * 2 ** 20,
 }
 
 
@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="reference rows of the batched workload, as a fraction of its sizes")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--batched-n", default="262144,1e6", metavar="LIST",
+                    help="samples per job of the batched leg (comma-separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 4 times (calibrates the HBM "
                          "byte counters of rocprofv3) and exit")
@@ -80,7 +82,8 @@ def main():
         import paper_2604_17066_amd as R
         ctx = R.Context(0)
         runs = {"scaling": lambda: scaling_leg(ctx, 5), "multi": lambda: multi_leg(ctx, 5),
-                "batched": lambda: batched_leg(ctx, args.batched_scale, args.batched_reps),
+                "batched": lambda: batched_leg(ctx, args.batched_scale, args.batched_reps,
+                                               tuple(int(float(v)) for v in args.batched_n.split(","))),
                 "stage1": lambda: stage1_leg(ctx, False), "global": lambda: global_leg(ctx),
                 "flow": lambda: flow_leg(ctx)}
         print(json.dumps({name: runs[name]() for name in args.only_legs.split(",")}))
@@ -275,7 +278,8 @@ def main():
         extra["scaling_count_mode"] = scaling_leg(
             ctx, reps, None if args.no_cpu_baseline else args.cpu_seconds)
         extra["multi_state"] = multi_leg(ctx, reps)
-        extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps)
+        extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps,
+                                                tuple(int(float(v)) for v in args.batched_n.split(",")))
         extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
         extra["global_connectivity"] = global_leg(ctx)
         extra["max_flow"] = flow_leg(ctx)
@@ -648,6 +652,16 @@ def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000)):
             return plan.results()[0]
 
         batched_ms, est = timed(run_plan)
+        # What the tuner chose per segment (one segment per graph): the
+        # cache's entries in the order of the graphs' reference rows.
+        with open(cache) as f:
+            entries = json.load(f)
+        names = {0: "cascade", 1: "popcount per job", 2: "int8 per job", 3: "fp4 per job",
+                 4: "persistent cascade"}
+        choices = sorted(({"key": k.split("/", 2)[2], "choice": names.get(v["choice"], "?"),
+                           "tail": v["tail"], "first": v["first"], "growth": v["growth"],
+                           "split": v["split"], "classify_ms": v["ms"]} for k, v in entries.items()),
+                         key=lambda e: e["key"])
         same = all(a["P"] == b["P"] and a["n_u"] == b["n_u"] for a, b in zip(est, plain_est))
         plan.close()
         se = max(e["se"] for e in est)
@@ -660,7 +674,7 @@ def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000)):
                         "speedup_vs_plain": plain_ms / batched_ms,
                         "speedup_vs_plain_popcount": pop_ms / batched_ms,
                         "plan_create_s": create_s, "plan_create_from_cache_s": create_cached_s,
-                        "identical_estimates": same, "max_se": se,
+                        "identical_estimates": same, "max_se": se, "tuned_segments": choices,
                         "nominal_tests_per_s_batched": total_tests / (batched_ms * 1e-3)}
         del jobs
         torch.cuda.empty_cache()

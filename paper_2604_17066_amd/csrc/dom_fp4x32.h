@@ -260,7 +260,10 @@ __device__ __forceinline__ void load_samples32(const uint32_t* __restrict__ xs, 
                                                v4i (&bf)[MT][KS], bool (&valid)[MT]) {
     const int col = lane & 31, half = lane >> 5;
     // Reads from clamped positions, all issued before any is used (reads
-    // behind a condition make the wait counts cover every path).
+    // behind a condition make the wait counts cover every path).  Each
+    // sample word is read once: the non-temporal hint keeps the stream from
+    // evicting the reference fragments, which every block of an XCD re-reads
+    // from its L2 (HBM fetch per graph2 launch 107 -> 63 MiB).
     uint32_t raw[MT][KS];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -269,7 +272,7 @@ __device__ __forceinline__ void load_samples32(const uint32_t* __restrict__ xs, 
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int w = 2 * s + half;
-            raw[t][s] = xs[static_cast<int64_t>(w < W ? w : W - 1) * stride + hc];
+            raw[t][s] = __builtin_nontemporal_load(xs + static_cast<int64_t>(w < W ? w : W - 1) * stride + hc);
         }
     }
 #pragma unroll

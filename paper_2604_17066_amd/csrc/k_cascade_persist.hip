@@ -615,6 +615,10 @@ int group_size(int KS) { return 32 * casc_tiles32(KS); }
 
 }  // namespace
 
+bool casc_persist_supported(const rsr_refs* refs) {
+    return refs->KS > 0 && resident_blocks(refs, 1) > 0;
+}
+
 // Grid of the persistent launch for N samples: the resident blocks, at most
 // kMaxRegions, and no more than the samples can keep busy.
 int casc_persist_grid(const rsr_refs* refs, int64_t N, int cus) {

@@ -274,8 +274,11 @@ __device__ __forceinline__ void mfma_pass(const v4i (&bf)[MT][KS], const v4i* __
 //   FP4:  nibbles 32*grp .. +31 of k-step s are bits 128 s + 32 grp .. +31,
 //         i.e. the whole word 4 s + grp.
 // The reference fragments use the same positions, so A and B agree on the k
-// of every operand element.
-template <int KS, int MT, bool FP4>
+// of every operand element.  NT: the samples are read once per launch (the
+// whole-set classification), so a non-temporal hint keeps them from evicting
+// the reference fragments from L2; the cascade's split rounds read theirs
+// once per chunk and keep them cached.
+template <int KS, int MT, bool FP4, bool NT = false>
 __device__ __forceinline__ void load_samples(const uint32_t* __restrict__ xs, int64_t stride,
                                              int64_t count, int W, int64_t wbase, int col, int grp,
                                              const uint32_t* __restrict__ done, v4i (&bf)[MT][KS],
@@ -293,7 +296,8 @@ __device__ __forceinline__ void load_samples(const uint32_t* __restrict__ xs, in
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int w = FP4 ? 4 * s + grp : 2 * s + (grp >> 1);
-            raw[t][s] = xs[static_cast<int64_t>(w < W ? w : W - 1) * stride + hc];
+            const uint32_t* at = xs + static_cast<int64_t>(w < W ? w : W - 1) * stride + hc;
+            raw[t][s] = NT ? __builtin_nontemporal_load(at) : *at;
         }
     }
 #pragma unroll
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_mfma(
 
     v4i bf[MT][KS];
     bool valid[MT];
-    load_samples<KS, MT, FP4>(xs, N, N, W, wbase, col, grp, nullptr, bf, valid);
+    load_samples<KS, MT, FP4, true>(xs, N, N, W, wbase, col, grp, nullptr, bf, valid);
 
     int accL[MT], accU[MT];  // 0 = no match yet in both modes
     bool none[MT];

@@ -770,7 +770,8 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         // then outnumber what the round kernels split well); otherwise, and
         // for the popcount form, the round kernels.
         const int64_t n_max = refs->R_L > refs->R_U ? refs->R_L : refs->R_U;
-        const bool persist = form == RSR_AUTO && refs->KS > 0 && n_max >= rsr::kPersistRows;
+        const bool persist = form == RSR_AUTO && refs->KS4 > 0 && n_max >= rsr::kPersistRows &&
+                             rsr::casc_persist_supported(refs);
         const int64_t stride = persist ? rsr::casc_persist_stride(refs, N, ctx->cu_count) : N;
         const int64_t state_words = persist ? rsr::casc_persist_state_words(stride, refs->KS) : 0;
         rsr_status st = ensure_cascade(ctx, refs->W, stride, state_words);

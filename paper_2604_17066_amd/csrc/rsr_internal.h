@@ -310,6 +310,8 @@ int64_t casc_persist_state_words(int64_t stride, int KS);
 // Compact-buffer capacity (cb.stride) the persistent cascade needs for N
 // samples: N plus the slack of its per-block output regions.
 int64_t casc_persist_stride(const rsr_refs* refs, int64_t N, int cus);
+// Whether the persistent cascade is built for the handle's width.
+bool casc_persist_supported(const rsr_refs* refs);
 // Round 0 of the cascade in the FP4 32 x 32 form (k_casc_head.hip): rows
 // [0, 32) of both sides over all samples of seg; flags the decided samples
 // (all samples when last) and packs the others into cb.words[0] / index[0] /

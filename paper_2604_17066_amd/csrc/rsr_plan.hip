@@ -31,7 +31,9 @@
 
 namespace {
 
-enum Choice { kCascade = 0, kBitsPerJob = 1, kMfmaPerJob = 2, kMfma4PerJob = 3 };
+// kPersist: the persistent LABEL cascade (one round-0 launch and one
+// cooperative launch for every later round, over all jobs of the segment).
+enum Choice { kCascade = 0, kBitsPerJob = 1, kMfmaPerJob = 2, kMfma4PerJob = 3, kPersist = 4 };
 
 struct Segment {
     const rsr_refs* refs = nullptr;
@@ -147,7 +149,7 @@ class CacheReader {
             if (eat('}')) break;
             return false;
         }
-        return seen == 63 && e.choice >= kCascade && e.choice <= kMfma4PerJob &&
+        return seen == 63 && e.choice >= kCascade && e.choice <= kPersist &&
                (e.choice != kCascade || (e.first >= 1 && e.growth >= 2 && e.split >= 1));
     }
 };
@@ -175,6 +177,8 @@ struct rsr_plan {
     int64_t casc_cap = 0;
     int casc_w = 0;
     uint64_t* d_casc_counters = nullptr;
+    uint32_t* d_casc_state = nullptr;  // persistent cascade state (zeroed per launch)
+    int64_t casc_state_words = 0;
     int32_t* d_list = nullptr;
     uint64_t* d_list_counter = nullptr;
     hipStream_t cap = nullptr;
@@ -233,6 +237,18 @@ hipError_t enqueue_sample(const rsr_plan* p, int si, hipStream_t st) {
 hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice choice,
                             const rsr::CascadeShape& shape) {
     const Segment& s = p->segs[si];
+    if (choice == kPersist) {
+        // counters[15] is the barrier time-out flag, cleared once per run at
+        // the start of the graph and copied back with the counts.
+        const rsr::CascadeBuffers cb = casc_buffers(p);
+        hipError_t e = rsr::launch_fill_u64(st, reinterpret_cast<uint64_t*>(p->d_casc_state),
+                                            (p->casc_state_words + 1) / 2, 0);
+        if (e != hipSuccess) return e;
+        return rsr::launch_casc_persist(st, s.refs, seg_src(p, s, si), cb, rsr::mfma_head_shape(),
+                                        p->d_casc_state,
+                                        reinterpret_cast<unsigned long long*>(p->d_casc_counters + 15),
+                                        p->ctx->cu_count);
+    }
     if (choice == kCascade) {
         const rsr::CascadeBuffers cb = casc_buffers(p);
         hipError_t e = rsr::launch_fill_u64(st, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0);
@@ -295,6 +311,7 @@ bool choice_runs(const Segment& s) {
         case kBitsPerJob: return true;
         case kMfmaPerJob: return s.refs->KS > 0;
         case kMfma4PerJob: return s.refs->KS4 > 0;
+        case kPersist: return s.refs->consistent && rsr::casc_persist_supported(s.refs);
     }
     return false;
 }
@@ -363,7 +380,15 @@ rsr_status tune_segment(rsr_plan* p, int si) {
         if (s.refs->KS4 > 0) forms.push_back({kCascade, rsr::mfma_tail_shape()});
         if (s.refs->KS4 > 0 && rsr::casc_head_supported(s.refs))
             forms.push_back({kCascade, rsr::mfma_head_shape()});
+        if (rsr::casc_persist_supported(s.refs)) forms.push_back({kPersist, rsr::mfma_head_shape()});
         st = trial(forms);
+        // The persistent cascade keeps its own round sizes.
+        if (st != RSR_OK || s.choice == kPersist) {
+            s.tuned_ms = best / 2.0f;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return st;
+        }
         const bool tail = s.shape.mfma_tail, head = s.shape.mfma_head;
         std::vector<Cand> shapes;
         // The matrix-core round 0 is one 32-row tile per side.
@@ -392,8 +417,8 @@ void free_plan(rsr_plan* p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     void* dev[] = {p->d_jobs, p->d_offsets, p->d_counts, p->d_count_part, p->d_grad_part,
-                   p->d_casc_words, p->d_casc_index, p->d_casc_counters, p->d_list,
-                   p->d_list_counter};
+                   p->d_casc_words, p->d_casc_index, p->d_casc_counters, p->d_casc_state,
+                   p->d_list, p->d_list_counter};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->h_counts) (void)hipHostFree(p->h_counts);
@@ -460,9 +485,14 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             s.W = jb.refs->W;
             s.choice = jb.refs->consistent ? kCascade : kBitsPerJob;
             // Untuned, a cascade takes the matrix-core rounds when the
-            // reference handle has FP4 operands, as rsr_classify's automatic
+            // reference handle has FP4 operands, and the persistent cascade
+            // from kPersistRows rows per side, as rsr_classify's automatic
             // form does.
             if (jb.refs->KS4 > 0) s.shape = rsr::mfma_tail_shape();
+            const int64_t rows = std::max(jb.refs->R_L, jb.refs->R_U);
+            if (jb.refs->consistent && jb.refs->KS4 > 0 && rows >= rsr::kPersistRows &&
+                rsr::casc_persist_supported(jb.refs))
+                s.choice = kPersist;
             p->segs.push_back(s);
             it = p->segs.end() - 1;
         }
@@ -520,8 +550,22 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
         max_grad = std::max(max_grad, static_cast<int64_t>(s.jobs.size()) *
                                           (static_cast<int64_t>(s.W) * bx * 32 + bx));
     }
-    p->casc_cap = max_total;
+    // The persistent cascade's compact buffers hold per-block regions with
+    // some slack beyond the segment's samples; its state holds one ticket per
+    // group of them.
+    int64_t cap = max_total, state_words = 0;
+    for (const Segment& s : p->segs) {
+        if (!s.refs->consistent || !rsr::casc_persist_supported(s.refs)) continue;
+        const int64_t sc = rsr::casc_persist_stride(s.refs, s.total, ctx->cu_count);
+        cap = std::max(cap, sc);
+    }
+    for (const Segment& s : p->segs) {
+        if (!s.refs->consistent || !rsr::casc_persist_supported(s.refs)) continue;
+        state_words = std::max(state_words, rsr::casc_persist_state_words(cap, s.refs->KS));
+    }
+    p->casc_cap = cap;
     p->casc_w = static_cast<int>(max_words);
+    p->casc_state_words = state_words;
     hipError_t e = hipSuccess;
     auto dmalloc = [&](void** ptr, size_t bytes) {
         if (e == hipSuccess) e = rsr::dev_malloc(ptr, bytes > 0 ? bytes : 8);
@@ -533,15 +577,18 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             sizeof(uint64_t) * 8 * rsr::kMaxReduceBlocks * max_jobs);
     dmalloc(reinterpret_cast<void**>(&p->d_grad_part), sizeof(uint32_t) * max_grad);
     dmalloc(reinterpret_cast<void**>(&p->d_casc_words),
-            sizeof(uint32_t) * 2 * static_cast<size_t>(max_words) * max_total);
-    dmalloc(reinterpret_cast<void**>(&p->d_casc_index), sizeof(int32_t) * 4 * max_total);
+            sizeof(uint32_t) * 2 * static_cast<size_t>(max_words) * cap);
+    dmalloc(reinterpret_cast<void**>(&p->d_casc_index), sizeof(int32_t) * 4 * cap);
+    if (state_words > 0)
+        dmalloc(reinterpret_cast<void**>(&p->d_casc_state),
+                sizeof(uint32_t) * static_cast<size_t>((state_words + 1) / 2 * 2));
     dmalloc(reinterpret_cast<void**>(&p->d_casc_counters),
             sizeof(uint64_t) * rsr::CascadeBuffers::kCounterU64);
     dmalloc(reinterpret_cast<void**>(&p->d_list), sizeof(int32_t) * max_total);
     dmalloc(reinterpret_cast<void**>(&p->d_list_counter), sizeof(uint64_t) * 2);
     dmalloc(reinterpret_cast<void**>(&p->d_G_all), sizeof(float) * p->G_total);
     if (e == hipSuccess)
-        e = rsr::host_malloc(&p->h_counts, sizeof(uint64_t) * 8 * n_jobs);
+        e = rsr::host_malloc(&p->h_counts, sizeof(uint64_t) * (8 * n_jobs + 1));
     if (e == hipSuccess)
         e = rsr::host_malloc(&p->h_G_all, sizeof(float) * (p->G_total + 1));
     if (e == hipSuccess)
@@ -550,6 +597,9 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
     if (e == hipSuccess)
         e = hipMemcpy(p->d_offsets, host_offsets.data(), sizeof(int64_t) * host_offsets.size(),
                       hipMemcpyHostToDevice);
+    // The persistent cascade's time-out flag (counters[15]) must read 0 in
+    // the tuner's trials too.
+    if (e == hipSuccess) e = hipMemset(p->d_casc_counters, 0, sizeof(uint64_t) * 16);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         free_plan(p);
@@ -602,6 +652,7 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
     }
     // Record the whole plan.
     e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = rsr::launch_fill_u64(p->cap, p->d_casc_counters + 15, 1, 0);
     for (size_t si = 0; si < p->segs.size() && e == hipSuccess; ++si) {
         const Segment& s = p->segs[si];
         e = enqueue_sample(p, static_cast<int>(si), p->cap);
@@ -611,6 +662,9 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_counts, p->d_counts, sizeof(uint64_t) * 8 * n_jobs,
                            hipMemcpyDeviceToHost, p->cap);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_counts + 8 * static_cast<size_t>(n_jobs), p->d_casc_counters + 15,
+                           sizeof(uint64_t), hipMemcpyDeviceToHost, p->cap);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_G_all, p->d_G_all, sizeof(float) * p->G_total,
                            hipMemcpyDeviceToHost, p->cap);
@@ -638,6 +692,8 @@ rsr_status rsr_plan_results(rsr_plan* p, rsr_estimate_t* est, float* G_host) {
     if (!est) return pfail(p->ctx, RSR_EINVAL, "NULL estimate array");
     rsr_ctx* ctx = p->ctx;
     PLAN_HIP(ctx, ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize());
+    if (p->h_counts[8 * p->jobs.size()] != 0)
+        return pfail(ctx, RSR_EHIP, "a persistent classification timed out at a grid barrier");
     size_t g_off = 0;
     for (size_t j = 0; j < p->jobs.size(); ++j) {
         const uint64_t* c = p->h_counts + static_cast<size_t>(p->pos[j]) * 8;

@@ -177,27 +177,33 @@ def test_plan_tuning_cache(rsr_ctx, tmp_path):
     assert bad.read_text() == '{"x": {"choice": 0}}'
 
 
-@pytest.mark.parametrize("tail,first,growth,split", [(0, 16, 4, 64), (1, 16, 6, 256),
-                                                     (2, 32, 4, 64), (2, 32, 8, 256)])
-def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, tail, first, growth, split):
-    """Every cascade shape a tuning cache can name (popcount rounds, matrix-core
-    rounds after round 0, matrix-core rounds from round 0 on) gives the plain
-    path's flags, Y and estimates on uneven jobs sharing a launch."""
+@pytest.mark.parametrize("choice,tail,first,growth,split", [(0, 0, 16, 4, 64), (0, 1, 16, 6, 256),
+                                                            (0, 2, 32, 4, 64), (0, 2, 32, 8, 256),
+                                                            (4, 2, 32, 6, 256)])
+def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, growth, split):
+    """Every cascade a tuning cache can name (popcount rounds, matrix-core
+    rounds after round 0, matrix-core rounds from round 0 on, the persistent
+    cascade: choice 4) gives the plain path's flags, Y and estimates on uneven
+    jobs sharing a launch, on two runs of the plan."""
     import json
     path = tmp_path / "tune.json"
     jobs, systems = _small_batch(rsr_ctx, n_scen=2, graphs=(1, 3), Ns=(20_000, 3_001, 777))
     R.Plan(rsr_ctx, jobs, tune=str(path)).close()
     entries = json.loads(path.read_text())
     for e in entries.values():
-        e.update(choice=0, first=first, growth=growth, split=split, tail=tail)
+        e.update(choice=choice, first=first, growth=growth, split=split, tail=tail)
     path.write_text(json.dumps(entries))
     plan = R.Plan(rsr_ctx, jobs, tune=str(path))
-    plan.run()
-    est, _ = plan.results()
-    for k, jb in enumerate(jobs):
-        pe, pb = _plain(rsr_ctx, jb)
-        b = jb["buffers"]
-        np.testing.assert_array_equal(_np(b.flags), _np(pb.flags), err_msg=f"job {k}")
-        np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k}")
-        assert est[k]["P"] == pe["P"] and est[k]["n_u"] == pe["n_u"], k
+    for rep in range(2):
+        for jb in jobs:
+            jb["buffers"].flags.fill_(7)
+        torch.cuda.synchronize()
+        plan.run()
+        est, _ = plan.results()
+        for k, jb in enumerate(jobs):
+            pe, pb = _plain(rsr_ctx, jb)
+            b = jb["buffers"]
+            np.testing.assert_array_equal(_np(b.flags), _np(pb.flags), err_msg=f"job {k} run {rep}")
+            np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k} run {rep}")
+            assert est[k]["P"] == pe["P"] and est[k]["n_u"] == pe["n_u"], (k, rep)
     plan.close()
