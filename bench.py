@@ -263,6 +263,28 @@ def main():
         "rsr_step_speedup": (plain_ms + sample_ms + grad_ms + est_ms) / ms_per_step}
     log(f"plain MC (BFS on every sample): {plain_ms:.3f} ms, P={plain_P:.6f}")
 
+    # The same step as a one-job plan: its kernels captured once into a HIP
+    # graph, one graph launch and one synchronisation per step.
+    gbuf = R.Buffers(ctx, n, K, N)
+    plan = R.Plan(ctx, [{"model": model, "refs": refs, "system": system, "seed": seed, "N": N,
+                         "buffers": gbuf}], tune=False)
+    for _ in range(args.warmup):
+        plan.run()
+        g_est = plan.results()[0][0]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+        g_est = plan.results()[0][0]
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    plan.close()
+    step_kernels["graph_step"] = {"ms_per_step": graph_ms, "tests_per_s": tests / (graph_ms * 1e-3),
+                                  "identical_estimate": g_est["P"] == est["P"] and g_est["n_u"] == est["n_u"]}
+    log(f"step as a one-job captured plan: {graph_ms:.3f} ms/step "
+        f"(identical estimate: {step_kernels['graph_step']['identical_estimate']})")
+    del gbuf
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
