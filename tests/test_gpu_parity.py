@@ -504,3 +504,32 @@ def test_eval_all_graph_sizes(rsr_ctx, g_idx, level):
     got = _np(Y)
     np.testing.assert_array_equal(got, want)
     assert 0 < int(want.sum()) < N
+
+
+@pytest.mark.parametrize("g", range(8))
+def test_classify_forms_agree_every_width(rsr_ctx, g):
+    """The eight batched graphs (120 to 1250 edges: 4 to 40 packed words, 2 to
+    20 FP4 k-steps of 64) with 5 % of their reference rows: every form gives
+    the popcount form's COUNT flags and match counts and its LABEL flags, on a
+    ragged N; the oracle checks sampled indices."""
+    cfg = WL.configs.batched(n_scen=1, N=1, graphs=[g], ref_scale=0.05)
+    sd = cfg["systems"][0]
+    n, p = sd["n"], cfg["jobs"][0]["p"]
+    N = 5003
+    m, xs = _sample(rsr_ctx, p, 11, 0, 0, N)
+    refs = R.Refs(rsr_ctx, n, 2, sd["lower"], sd["upper"])
+    fc0, mt0 = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, R.RSR_POPCOUNT, want_match=True)
+    fc0, mt0 = _np(fc0).copy(), _np(mt0).view(np.uint32).copy()
+    fl0 = _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT)).copy()
+    for form in (R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO):
+        fc, mt = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, form, want_match=True)
+        np.testing.assert_array_equal(_np(fc), fc0, err_msg=f"COUNT flags, form {form}")
+        np.testing.assert_array_equal(_np(mt).view(np.uint32), mt0, err_msg=f"counts, form {form}")
+        fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
+        np.testing.assert_array_equal(_np(fl), fl0, err_msg=f"LABEL flags, form {form}")
+    idx = np.unique(np.concatenate([np.arange(0, N, 97), [N - 1]]))
+    x = oracle.sample_at(p, 11, 0, idx.astype(np.uint64))
+    oc, mL, mU = oracle.classify(sd["lower"], sd["upper"], x, mode=1)
+    np.testing.assert_array_equal(fc0[idx], oc)
+    np.testing.assert_array_equal(mt0[idx, 0], mL)
+    np.testing.assert_array_equal(mt0[idx, 1], mU)
