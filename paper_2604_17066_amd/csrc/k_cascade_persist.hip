@@ -39,12 +39,6 @@ namespace {
 using namespace mf;
 using namespace casc;
 
-#ifndef RSR_CASC_MT2_KS
-#define RSR_CASC_MT2_KS 10
-#endif
-#ifndef RSR_CASC_RING
-#define RSR_CASC_RING 2
-#endif
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
@@ -62,7 +56,13 @@ constexpr int kBarGroups = 64;
 constexpr int kLine = 32;
 
 // Sample tiles (32 samples) per wave in the matrix-core rounds.
-constexpr int casc_tiles32(int KS) { return KS <= RSR_CASC_MT2_KS ? 2 : 1; }
+// (Measured on the multi-state level, 10 k-steps: two tiles 0.29 ms, one
+// 0.31 ms.)
+constexpr int casc_tiles32(int KS) { return KS <= 10 ? 2 : 1; }
+
+// Register sets of a wave's read-ahead ring of A fragments (one tile read
+// ahead; three sets measured no faster).
+constexpr int kRing = 2;
 
 // Samples per lane in round 0.
 constexpr int r0_samples(int W) { return W <= 12 ? 4 : (W <= 24 ? 2 : 1); }
@@ -341,7 +341,7 @@ template <int W, int KS>
 __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
     constexpr int MT = casc_tiles32(KS);
     constexpr int G = 32 * MT;  // samples per wave item
-    constexpr int RING = KS <= 5 ? RSR_CASC_RING : 2;
+    constexpr int RING = kRing;
     constexpr int kPer = kMaxRegions / kBlock;
     __shared__ uint32_t s_prefix[kMaxRegions + 1];
     __shared__ uint32_t s_wave[kWaves];
