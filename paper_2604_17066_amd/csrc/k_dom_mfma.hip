@@ -680,6 +680,26 @@ __global__ __launch_bounds__(kBlock) void k_casc_mfma_round(
     }
 }
 
+// Blocks of `kernel` (kBlock threads) the device holds at once.  The
+// cascade's round kernels read their sample count on the device and loop
+// over it, so a grid beyond this only adds blocks that find no samples: the
+// host's bound (all N samples) would launch thousands of them for a round
+// that keeps a few thousand samples, in as many waves of one block per CU.
+// Cached per kernel and device (0: not yet known).
+int resident_blocks(const void* kernel, int (&cache)[RSR_MAX_DEVICES]) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= RSR_MAX_DEVICES) return 1 << 30;
+    if (cache[dev] == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
+            per_cu <= 0)
+            return 1 << 30;
+        cache[dev] = per_cu * cus;
+    }
+    return cache[dev];
+}
+
 template <int KS>
 hipError_t launch_round_ks(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
                            const uint32_t* csrc, int64_t cstride, const int32_t* src_idx,
@@ -689,8 +709,11 @@ hipError_t launch_round_ks(hipStream_t st, const rsr_refs* refs, const SegSrc& s
                            int64_t dst_stride, unsigned long long* dst_count, int last) {
     constexpr int MT = casc_sample_tiles<KS>();
     const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
+    static int cache[RSR_MAX_DEVICES] = {};
+    const int resident = resident_blocks(reinterpret_cast<const void*>(k_casc_mfma_round<KS, MT>), cache);
     int64_t bx = (max_count + per_block - 1) / per_block;
     if (bx > grid_cap) bx = grid_cap;
+    if (src_count && bx > resident) bx = resident;
     if (bx < 1) bx = 1;
     hipLaunchKernelGGL((k_casc_mfma_round<KS, MT>), dim3(static_cast<unsigned>(bx)), dim3(kBlock),
                        0, st, seg, csrc, cstride, src_idx, src_count, host_count, refs->W,
@@ -709,9 +732,12 @@ hipError_t launch_casc_ks(hipStream_t st, const rsr_refs* refs, const uint32_t* 
                           uint32_t* match) {
     constexpr int MT = casc_sample_tiles<KS>();
     const int64_t per_block = static_cast<int64_t>(kWaves) * 16 * MT;
+    static int cache[RSR_MAX_DEVICES] = {};
+    const int resident = resident_blocks(reinterpret_cast<const void*>(k_casc_mfma<KS, MT>), cache);
     int64_t bx = (max_count + per_block - 1) / per_block;
     const int64_t cap = grid_cap / chunks > 0 ? grid_cap / chunks : 1;
     if (bx > cap) bx = cap;
+    if (bx > resident / chunks) bx = resident / chunks;
     if (bx < 1) bx = 1;
     hipLaunchKernelGGL((k_casc_mfma<KS, MT>), dim3(static_cast<unsigned>(bx), chunks),
                        dim3(kBlock), 0, st, csrc, cstride, src_count, refs->W,
