@@ -384,7 +384,12 @@ typedef struct {
  *   a file path:      a JSON object whose keys name a device and a segment
  *                     shape (device name, CU count, packed words W, R_L, R_U,
  *                     consistency, matrix-core operands, jobs and samples per
- *                     job) and whose values are the chosen configuration.
+ *                     job) and whose values are the chosen configuration:
+ *                     {"choice": 0 cascade, 1 popcount per job, 2 int8
+ *                     per job, 3 FP4 per job, 4 persistent cascade;
+ *                     "first", "growth", "split": the cascade's round
+ *                     rows; "tail": 0 popcount rounds, 1 FP4 rounds after
+ *                     round 0, 2 FP4 rounds from round 0 on; "ms"}.
  *                     Segments whose key is present take the stored choice
  *                     without timing; the others are timed, and the file is
  *                     rewritten (via a temporary file and a rename) with the
@@ -399,7 +404,9 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
 rsr_status rsr_plan_run(rsr_plan* plan);
 /* Synchronises and copies the per-job estimates (host [n_jobs]) and, if
  * G_host is not NULL, every job's gradient concatenated in job order (host,
- * sum of n*K floats). */
+ * sum of n*K floats).  EHIP: a device error, or a persistent cascade of the
+ * run whose blocks did not all reach a grid barrier within its time limit
+ * (its flags are then not to be trusted). */
 rsr_status rsr_plan_results(rsr_plan* plan, rsr_estimate_t* est, float* G_host);
 rsr_status rsr_plan_destroy(rsr_plan* plan);
 
