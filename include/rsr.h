@@ -226,7 +226,11 @@ rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint3
  * and LABEL modes alike), RSR_MFMA_FP4 (the same contraction with FP4 E2M1
  * operands 0 / +-1 and fp32 accumulation, exact because every partial sum
  * is a small integer), RSR_AUTO (the cascade for LABEL mode on consistent
- * rows, else the FP4 form up to 1280 bits, else the popcount form).  Every form
+ * rows, else the FP4 form up to 1280 bits, else the popcount form).  The
+ * automatic cascade runs its rounds after round 0 in one persistent,
+ * cooperative launch from 16384 rows per side on (its grid barriers wait
+ * with a time limit; a barrier that timed out is reported as RSR_EHIP by the
+ * next rsr_estimate), and as one launch per round below that.  Every form
  * returns identical outputs.  EINVAL: refs built for another n/K, N <= 0,
  * NULL d_flags.  EUNSUPPORTED: a matrix-core form with n*(K-1) > 1280. */
 rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_samples,
