@@ -250,7 +250,9 @@ rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t*
 
 /* Reduces flags (and Y, if not NULL) to counts on the device, copies them to
  * the host, synchronises the stream and fills *out as rsr_estimate_t says.
- * With d_Y == NULL, n_u_up = 0 and P, se, cov are NaN (bounds only). */
+ * With d_Y == NULL, n_u_up = 0 and P, se, cov are NaN (bounds only).
+ * EHIP: a device error, or a persistent cascade since the previous call
+ * whose grid barrier timed out (the flag is cleared with the report). */
 rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
                         rsr_estimate_t* out);
 
