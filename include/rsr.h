@@ -426,6 +426,14 @@ rsr_status rsr_plan_destroy(rsr_plan* plan);
  * thread-safe with respect to concurrent library calls. */
 rsr_status rsr_debug_fail_alloc(int64_t after);
 
+/* For tests of the persistent cascade's time-out path: its grid barriers
+ * then wait at most `ticks` ticks of the 100 MHz real-time counter (0: a
+ * block that has to wait at all gives up at once, sets the error flag and
+ * leaves, so every launch still ends); a negative value restores the
+ * default of 10 s.  Applies to launches made after the call, on every
+ * context.  Not thread-safe with respect to concurrent library calls. */
+rsr_status rsr_debug_barrier_timeout(int64_t ticks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,6 +104,7 @@ SIGNATURES = {
     "rsr_plan_results": (ctypes.c_int, [_vp, ctypes.POINTER(rsr_estimate_t), _vp]),
     "rsr_plan_destroy": (ctypes.c_int, [_vp]),
     "rsr_debug_fail_alloc": (ctypes.c_int, [_i64]),
+    "rsr_debug_barrier_timeout": (ctypes.c_int, [_i64]),
 }
 
 _lib = None

@@ -48,8 +48,10 @@ constexpr int kMaxRegions = 2048;
 // Chunks of fewer row tiles than this (per side) are not worth their sample
 // loads.
 constexpr int kMinChunkTiles = 4;
-// Barrier time limit in ticks of the 100 MHz real-time counter (10 s).
+// Barrier time limit in ticks of the 100 MHz real-time counter (10 s);
+// rsr_debug_barrier_timeout changes it for tests of the time-out path.
 constexpr uint64_t kBarrierTimeout = 1000000000ull;
+uint64_t g_barrier_ticks = kBarrierTimeout;
 // Barrier: kBarGroups arrival counters, the top counter and the generation,
 // each on its own 128-byte line (32 u32).
 constexpr int kBarGroups = 64;
@@ -101,6 +103,7 @@ struct PersistArgs {
     uint32_t* state;                 // StateLayout
     StateLayout L;
     unsigned long long* err;         // set to 1 when a barrier times out
+    uint64_t timeout;                // barrier time limit (real-time counter ticks)
 };
 
 // ---- round 0 -----------------------------------------------------------------
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_r0(SegSrc seg, int w_real,
 // the groups.  A release fence before the arrival writes this block's earlier
 // stores back from its L2 (the L2s of the XCDs are not coherent); an acquire
 // fence after the barrier drops stale lines.
-__device__ bool grid_sync(uint32_t* bar, unsigned long long* err) {
+__device__ bool grid_sync(uint32_t* bar, unsigned long long* err, uint64_t timeout) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -235,7 +238,7 @@ __device__ bool grid_sync(uint32_t* bar, unsigned long long* err) {
             const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
             while (__hip_atomic_load(gen_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
-                if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeout) {
+                if (__builtin_amdgcn_s_memrealtime() - t0 > timeout) {
                     ok = 0;
                     __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_persist(PersistArgs a) {
     uint32_t* st = a.state;
     for (int r = 1; r < a.rounds; ++r) {
         const bool last = r + 1 == a.rounds;
-        if (r > 1 && !grid_sync(st + a.L.bar, a.err)) return;
+        if (r > 1 && !grid_sync(st + a.L.bar, a.err, a.timeout)) return;
         // Regions of this round's input (written by round r - 1) and the
         // prefix sum of their counts, in LDS.
         const int nreg = static_cast<int>(st[a.L.ngrid + r - 1]);
@@ -615,6 +618,10 @@ int group_size(int KS) { return 32 * casc_tiles32(KS); }
 
 }  // namespace
 
+void set_barrier_timeout(int64_t ticks) {
+    g_barrier_ticks = ticks < 0 ? kBarrierTimeout : static_cast<uint64_t>(ticks);
+}
+
 bool casc_persist_supported(const rsr_refs* refs) {
     return refs->KS > 0 && resident_blocks(refs, 1) > 0;
 }
@@ -679,6 +686,7 @@ hipError_t launch_casc_persist(hipStream_t st, const rsr_refs* refs, const SegSr
     a.stride = cb.stride;
     a.state = d_state;
     a.err = d_err;
+    a.timeout = g_barrier_ticks;
     a.L = StateLayout((cb.stride + group_size(refs->KS) - 1) / group_size(refs->KS));
     // Round 0: contiguous spans of whole block steps, at most kMaxRegions.
     const int64_t step = static_cast<int64_t>(kBlock) * r0_samples(refs->WR);

@@ -932,6 +932,11 @@ rsr_status rsr_importance(rsr_ctx* ctx, const rsr_model* model, const uint32_t* 
     return RSR_OK;
 }
 
+rsr_status rsr_debug_barrier_timeout(int64_t ticks) {
+    rsr::set_barrier_timeout(ticks);
+    return RSR_OK;
+}
+
 rsr_status rsr_debug_fail_alloc(int64_t after) {
     rsr::g_fail_countdown = after < 0 ? -1 : after;
     return RSR_OK;

@@ -312,6 +312,9 @@ int64_t casc_persist_state_words(int64_t stride, int KS);
 int64_t casc_persist_stride(const rsr_refs* refs, int64_t N, int cus);
 // Whether the persistent cascade is built for the handle's width.
 bool casc_persist_supported(const rsr_refs* refs);
+// Time limit of the persistent cascade's grid barriers (ticks of the 100 MHz
+// real-time counter; < 0: the default, 10 s).
+void set_barrier_timeout(int64_t ticks);
 // Round 0 of the cascade in the FP4 32 x 32 form (k_casc_head.hip): rows
 // [0, 32) of both sides over all samples of seg; flags the decided samples
 // (all samples when last) and packs the others into cb.words[0] / index[0] /

@@ -117,7 +117,7 @@ def test_null_arguments_rejected_without_device():
 
 def _status_functions():
     return [name for name, (res, _) in A.SIGNATURES.items()
-            if res is ctypes.c_int and name != "rsr_debug_fail_alloc"]
+            if res is ctypes.c_int and not name.startswith("rsr_debug_")]
 
 
 @pytest.mark.parametrize("name", _status_functions())
@@ -141,10 +141,16 @@ def test_every_status_function_is_covered():
     text = open(os.path.join(ROOT, "include", "rsr.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     declared = set(re.findall(r"rsr_status\s+(rsr_[a-z_0-9]+)\s*\(", text))
-    assert declared - {"rsr_debug_fail_alloc"} == set(_status_functions())
+    assert declared - {"rsr_debug_fail_alloc", "rsr_debug_barrier_timeout"} == set(_status_functions())
 
 
 def test_fail_alloc_hook_arms_and_disarms():
     lib = A.lib()
     assert lib.rsr_debug_fail_alloc(3) == A.RSR_OK
     assert lib.rsr_debug_fail_alloc(-1) == A.RSR_OK
+
+
+def test_barrier_timeout_hook_sets_and_restores():
+    lib = A.lib()
+    assert lib.rsr_debug_barrier_timeout(0) == A.RSR_OK
+    assert lib.rsr_debug_barrier_timeout(-1) == A.RSR_OK

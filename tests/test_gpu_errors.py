@@ -245,3 +245,36 @@ def test_injected_enomem_leaves_context_usable(rsr_ctx, target):
             break
     assert ok and failures >= 1, (target, failures)
     _check_path_still_exact(rsr_ctx)
+
+
+def test_persistent_barrier_timeout_is_reported(rsr_ctx):
+    """The persistent cascade's grid barriers wait with a time limit.  Forced
+    to zero from the host (rsr_debug_barrier_timeout), a block that would
+    wait gives up at once and sets the error flag, every launch still ends,
+    and the next rsr_estimate reports RSR_EHIP; with the default limit
+    restored, the same classification equals the oracle."""
+    cfg = WL.configs.batched(n_scen=1, N=1, graphs=[5], ref_scale=1.0)
+    sd = cfg["systems"][0]
+    n, p = sd["n"], cfg["jobs"][0]["p"]
+    N = 100_000
+    model = R.Model(rsr_ctx, p)
+    xs = R.rsr_sample(rsr_ctx, model, 7, 0, 0, N)
+    refs = R.Refs(rsr_ctx, n, 2, sd["lower"], sd["upper"])
+    assert max(refs.R_L, refs.R_U) >= 16_384  # the automatic form is persistent here
+    lib = A.lib()
+    try:
+        assert lib.rsr_debug_barrier_timeout(0) == A.RSR_OK
+        fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO)
+        with pytest.raises(R.RSRError) as ei:
+            R.rsr_estimate(rsr_ctx, fl, None, N)
+        assert ei.value.status == A.RSR_EHIP
+        assert "timed out" in str(ei.value)
+    finally:
+        lib.rsr_debug_barrier_timeout(-1)
+    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO)
+    est = R.rsr_estimate(rsr_ctx, fl, None, N)
+    idx = np.unique(np.concatenate([np.arange(0, N, 211), [N - 1]]))
+    x = oracle.sample_at(p, 7, 0, idx.astype(np.uint64))
+    want, _, _ = oracle.classify(sd["lower"], sd["upper"], x, mode=0)
+    np.testing.assert_array_equal(_np(fl)[idx], want)
+    assert est["n_L"] + est["n_U"] + est["n_u"] == N
