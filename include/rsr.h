@@ -431,7 +431,9 @@ rsr_status rsr_debug_fail_alloc(int64_t after);
  * block that has to wait at all gives up at once, sets the error flag and
  * leaves, so every launch still ends); a negative value restores the
  * default of 10 s.  Applies to launches made after the call, on every
- * context.  Not thread-safe with respect to concurrent library calls. */
+ * context, and to plans recorded after it (a plan keeps the limit it was
+ * recorded with).  Not thread-safe with respect to concurrent library
+ * calls. */
 rsr_status rsr_debug_barrier_timeout(int64_t ticks);
 
 #ifdef __cplusplus

@@ -207,3 +207,39 @@ def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, grow
             np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k} run {rep}")
             assert est[k]["P"] == pe["P"] and est[k]["n_u"] == pe["n_u"], (k, rep)
     plan.close()
+
+
+def test_plan_persistent_timeout_is_reported(rsr_ctx, tmp_path):
+    """A plan whose segments run the persistent cascade (choice 4 from a
+    tuning cache) reports a barrier time-out from rsr_plan_results as
+    RSR_EHIP: the limit is a launch argument, so it is forced to zero while
+    the plan is recorded.  A plan recorded with the default limit gives the
+    plain path's flags."""
+    import json
+    from paper_2604_17066_amd import _abi as A
+    path = tmp_path / "tune.json"
+    jobs, systems = _small_batch(rsr_ctx, n_scen=2, graphs=(3,), Ns=(60_000, 30_001))
+    R.Plan(rsr_ctx, jobs, tune=str(path)).close()
+    entries = json.loads(path.read_text())
+    for e in entries.values():
+        e.update(choice=4, first=32, growth=6, split=256, tail=2)
+    path.write_text(json.dumps(entries))
+    lib = A.lib()
+    try:
+        assert lib.rsr_debug_barrier_timeout(0) == A.RSR_OK
+        plan = R.Plan(rsr_ctx, jobs, tune=str(path))
+        plan.run()
+        with pytest.raises(R.RSRError) as ei:
+            plan.results()
+        assert ei.value.status == A.RSR_EHIP
+        plan.close()
+    finally:
+        lib.rsr_debug_barrier_timeout(-1)
+    plan = R.Plan(rsr_ctx, jobs, tune=str(path))
+    plan.run()
+    est, _ = plan.results()
+    for k, jb in enumerate(jobs):
+        pe, pb = _plain(rsr_ctx, jb)
+        np.testing.assert_array_equal(_np(jb["buffers"].flags), _np(pb.flags), err_msg=f"job {k}")
+        assert est[k]["P"] == pe["P"], k
+    plan.close()
