@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", default="auto", choices=["auto", "popcount", "mfma", "mfma_fp4"])
+    ap.add_argument("--form", default="auto", choices=["auto", "popcount", "mfma", "mfma_fp4", "persist"])
     ap.add_argument("--skip-legs", action="store_true",
                     help="only the graph2 step (no scaling / multi-state / batched legs)")
     ap.add_argument("--only-legs", default="", metavar="LIST",
@@ -100,7 +100,7 @@ def main():
     import workloads as WL
 
     form = {"auto": R.RSR_AUTO, "popcount": R.RSR_POPCOUNT, "mfma": R.RSR_MFMA,
-            "mfma_fp4": R.RSR_MFMA_FP4}[args.form]
+            "mfma_fp4": R.RSR_MFMA_FP4, "persist": R.RSR_PERSIST}[args.form]
     t0 = time.time()
     cfg = WL.configs.graph2()
     N, n, K = cfg["N"], cfg["n"], cfg["K"]

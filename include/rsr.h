@@ -65,7 +65,7 @@ typedef enum {
 } rsr_status;
 
 enum { RSR_LABEL = 0, RSR_COUNT = 1 };                  /* rsr_classify mode */
-enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2, RSR_MFMA_FP4 = 3 };  /* rsr_classify form */
+enum { RSR_AUTO = 0, RSR_POPCOUNT = 1, RSR_MFMA = 2, RSR_MFMA_FP4 = 3, RSR_PERSIST = 4 };  /* rsr_classify form */
 enum { RSR_UNKNOWN_ONLY = 0, RSR_ALL = 1 };             /* rsr_eval_unknown which */
 enum { RSR_SYS_ST_CONNECTIVITY = 1, RSR_SYS_GLOBAL_CONNECTIVITY = 2, RSR_SYS_MAX_FLOW = 3,
        RSR_SYS_HOST_CALLBACK = 4 };  /* rsr_system_desc kind */
@@ -226,13 +226,16 @@ rsr_status rsr_sample(rsr_ctx* ctx, const rsr_model* model, uint64_t seed, uint3
  * and LABEL modes alike), RSR_MFMA_FP4 (the same contraction with FP4 E2M1
  * operands 0 / +-1 and fp32 accumulation, exact because every partial sum
  * is a small integer), RSR_AUTO (the cascade for LABEL mode on consistent
- * rows, else the FP4 form up to 1280 bits, else the popcount form).  The
- * automatic cascade runs its rounds after round 0 in one persistent,
- * cooperative launch from 16384 rows per side on (its grid barriers wait
- * with a time limit; a barrier that timed out is reported as RSR_EHIP by the
- * next rsr_estimate), and as one launch per round below that.  Every form
- * returns identical outputs.  EINVAL: refs built for another n/K, N <= 0,
- * NULL d_flags.  EUNSUPPORTED: a matrix-core form with n*(K-1) > 1280. */
+ * rows, else the FP4 form up to 1280 bits, else the popcount form),
+ * RSR_PERSIST (the cascade with its rounds after round 0 in one persistent,
+ * cooperative launch; its grid barriers wait with a time limit, and a
+ * barrier that timed out is reported as RSR_EHIP by the next rsr_estimate).
+ * The automatic cascade runs one launch per round, each round after round 0
+ * 6 times the rows of the one before, 8 times from 16384 rows per side on.
+ * Every form returns identical outputs.  EINVAL: refs built for another n/K,
+ * N <= 0, NULL d_flags.  EUNSUPPORTED: a matrix-core form (RSR_PERSIST
+ * included) with n*(K-1) > 1280; RSR_PERSIST in COUNT mode, on inconsistent
+ * rows or with N > 2^31-1. */
 rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_samples,
                         int64_t N, int32_t mode, int32_t form, uint8_t* d_flags,
                         uint32_t* d_match);

@@ -7,7 +7,8 @@ does not need a GPU; creating a Context does, and there is no CPU fallback.
 """
 from ._abi import (  # noqa: F401
     RSR_OK, RSR_EINVAL, RSR_ENOMEM, RSR_EHIP, RSR_EUNSUPPORTED, RSR_LABEL, RSR_COUNT, RSR_AUTO,
-    RSR_POPCOUNT, RSR_MFMA, RSR_MFMA_FP4, RSR_UNKNOWN_ONLY, RSR_ALL, RSR_SYS_HOST_CALLBACK,
+    RSR_POPCOUNT, RSR_MFMA, RSR_MFMA_FP4, RSR_PERSIST, RSR_UNKNOWN_ONLY, RSR_ALL,
+    RSR_SYS_HOST_CALLBACK,
     RSRError, lib,
 )
 from .api import (  # noqa: F401

@@ -13,7 +13,7 @@ LIB_PATH = os.environ.get("RSR_LIB") or os.path.join(_HERE, "librsr.so")
 
 RSR_OK, RSR_EINVAL, RSR_ENOMEM, RSR_EHIP, RSR_EUNSUPPORTED = 0, 1, 2, 3, 4
 RSR_LABEL, RSR_COUNT = 0, 1
-RSR_AUTO, RSR_POPCOUNT, RSR_MFMA, RSR_MFMA_FP4 = 0, 1, 2, 3
+RSR_AUTO, RSR_POPCOUNT, RSR_MFMA, RSR_MFMA_FP4, RSR_PERSIST = 0, 1, 2, 3, 4
 RSR_UNKNOWN_ONLY, RSR_ALL = 0, 1
 RSR_SYS_ST_CONNECTIVITY = 1
 RSR_SYS_GLOBAL_CONNECTIVITY = 2

@@ -751,12 +751,18 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
     if (!refs || !d_samples || !d_flags) return fail(ctx, RSR_EINVAL, "NULL argument");
     if (N <= 0) return fail(ctx, RSR_EINVAL, "N must be > 0");
     if (mode != RSR_LABEL && mode != RSR_COUNT) return fail(ctx, RSR_EINVAL, "bad mode");
-    if (form != RSR_AUTO && form != RSR_POPCOUNT && form != RSR_MFMA && form != RSR_MFMA_FP4)
+    if (form != RSR_AUTO && form != RSR_POPCOUNT && form != RSR_MFMA && form != RSR_MFMA_FP4 &&
+        form != RSR_PERSIST)
         return fail(ctx, RSR_EINVAL, "bad form");
     if (refs->ctx->device != ctx->device) return fail(ctx, RSR_EINVAL, "refs on another device");
     DeviceGuard g(ctx->device);
-    if ((form == RSR_MFMA && refs->KS == 0) || (form == RSR_MFMA_FP4 && refs->KS4 == 0))
+    if ((form == RSR_MFMA && refs->KS == 0) ||
+        ((form == RSR_MFMA_FP4 || form == RSR_PERSIST) && refs->KS4 == 0))
         return fail(ctx, RSR_EUNSUPPORTED, "matrix-core form needs n*(K-1) <= 1280");
+    if (form == RSR_PERSIST &&
+        (mode != RSR_LABEL || !refs->consistent || N > 0x7FFFFFFFll || !rsr::casc_persist_supported(refs)))
+        return fail(ctx, RSR_EUNSUPPORTED,
+                    "the persistent cascade takes LABEL mode on consistent rows, N <= 2^31-1");
     uint32_t* match = mode == RSR_COUNT ? d_match : nullptr;
     // RSR_AUTO: the cascade for LABEL on consistent rows (each sample stops at
     // its first match); otherwise the FP4 matrix-core form, which makes the
@@ -765,13 +771,10 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         form = RSR_MFMA_FP4;
     const bool matrix = form == RSR_MFMA || form == RSR_MFMA_FP4;
     if (mode == RSR_LABEL && !matrix && refs->consistent && N <= 0x7FFFFFFFll) {
-        // The automatic form with matrix-core operands runs the rounds after
-        // round 0 in one persistent launch when the rows are many (its rounds
-        // then outnumber what the round kernels split well); otherwise, and
-        // for the popcount form, the round kernels.
+        // RSR_PERSIST runs the rounds after round 0 in one persistent
+        // launch; the automatic and popcount forms run one launch per round.
         const int64_t n_max = refs->R_L > refs->R_U ? refs->R_L : refs->R_U;
-        const bool persist = form == RSR_AUTO && refs->KS4 > 0 && n_max >= rsr::kPersistRows &&
-                             rsr::casc_persist_supported(refs);
+        const bool persist = form == RSR_PERSIST;
         const int64_t stride = persist ? rsr::casc_persist_stride(refs, N, ctx->cu_count) : N;
         const int64_t state_words = persist ? rsr::casc_persist_state_words(stride, refs->KS) : 0;
         rsr_status st = ensure_cascade(ctx, refs->W, stride, state_words);
@@ -787,11 +790,12 @@ rsr_status rsr_classify(rsr_ctx* ctx, const rsr_refs* refs, const uint32_t* d_sa
         cb.counters = ctx->ws.casc_counters;
         cb.regions = reinterpret_cast<uint32_t*>(ctx->ws.casc_counters + 16);
         // The automatic form runs the rounds after round 0 in the FP4
-        // matrix-core form when the handle has its operands; the popcount
-        // form stays popcount.
-        const rsr::CascadeShape shape = form == RSR_AUTO && refs->KS4 > 0
-                                            ? rsr::mfma_tail_shape()
-                                            : rsr::CascadeShape{};
+        // matrix-core form when the handle has its operands, with faster
+        // growing rounds from kWideRows rows per side on; the popcount form
+        // stays popcount.
+        const rsr::CascadeShape shape = form != RSR_AUTO || refs->KS4 == 0 ? rsr::CascadeShape{}
+                                        : n_max >= rsr::kWideRows        ? rsr::mfma_wide_shape()
+                                                                         : rsr::mfma_tail_shape();
         if (persist) {
             RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, reinterpret_cast<uint64_t*>(ctx->ws.casc_state),
                                               (state_words + 1) / 2, 0));

@@ -265,11 +265,23 @@ inline CascadeShape mfma_head_shape() {
     return s;
 }
 
-// Rows per side from which the automatic LABEL form runs the persistent
-// cascade instead of the round kernels (measured on MI355X: 0.32 against
-// 0.44 ms at 2.5e4 rows of 590 bits, 0.22 against 0.16 ms at 1e4 rows of 295
-// bits, N = 1e6).
-constexpr int64_t kPersistRows = 16384;
+// Shape with the matrix-core tail for many rows: growth 8 reaches the last
+// row in fewer rounds, and larger chunks keep each split round's waves busy.
+inline CascadeShape mfma_wide_shape() {
+    CascadeShape s;
+    s.first = 16;
+    s.growth = 8;
+    s.split_rows = 512;
+    s.mfma_tail = true;
+    return s;
+}
+
+// Rows per side from which the automatic LABEL form takes mfma_wide_shape
+// (measured on MI355X on the three-state levels of graph2 and on 4.4e4 to 2e5
+// reference rows: 0.79 to 0.99 of the persistent cascade's time and 0.80 to
+// 0.96 of mfma_tail_shape's; on graph2's 1e4 rows per side mfma_tail_shape is
+// the faster by 18%).
+constexpr int64_t kWideRows = 16384;
 
 // Largest refs->KS (64-wide k-steps) of the matrix-core round 0.
 constexpr int kMaxHeadSteps = 10;

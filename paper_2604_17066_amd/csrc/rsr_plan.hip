@@ -377,7 +377,10 @@ rsr_status tune_segment(rsr_plan* p, int si) {
     rsr_status st = RSR_OK;
     if (s.refs->consistent) {
         std::vector<Cand> forms = {{kCascade, rsr::CascadeShape{}}};
-        if (s.refs->KS4 > 0) forms.push_back({kCascade, rsr::mfma_tail_shape()});
+        if (s.refs->KS4 > 0) {
+            forms.push_back({kCascade, rsr::mfma_tail_shape()});
+            forms.push_back({kCascade, rsr::mfma_wide_shape()});
+        }
         if (s.refs->KS4 > 0 && rsr::casc_head_supported(s.refs))
             forms.push_back({kCascade, rsr::mfma_head_shape()});
         if (rsr::casc_persist_supported(s.refs)) forms.push_back({kPersist, rsr::mfma_head_shape()});
@@ -394,7 +397,7 @@ rsr_status tune_segment(rsr_plan* p, int si) {
         // The matrix-core round 0 is one 32-row tile per side.
         const std::vector<int> firsts = head ? std::vector<int>{32} : std::vector<int>{8, 16, 32, 64};
         const int growths[] = {4, 8};
-        const int splits[] = {64, 256};
+        const int splits[] = {64, 256, 512};
         for (int f : firsts)
             for (int g : growths)
                 for (int sp : splits)
@@ -484,15 +487,12 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             s.K = jb.refs->K;
             s.W = jb.refs->W;
             s.choice = jb.refs->consistent ? kCascade : kBitsPerJob;
-            // Untuned, a cascade takes the matrix-core rounds when the
-            // reference handle has FP4 operands, and the persistent cascade
-            // from kPersistRows rows per side, as rsr_classify's automatic
-            // form does.
-            if (jb.refs->KS4 > 0) s.shape = rsr::mfma_tail_shape();
+            // Untuned, a cascade takes the shape of rsr_classify's automatic
+            // form: matrix-core rounds when the reference handle has FP4
+            // operands, growing faster from kWideRows rows per side on.
             const int64_t rows = std::max(jb.refs->R_L, jb.refs->R_U);
-            if (jb.refs->consistent && jb.refs->KS4 > 0 && rows >= rsr::kPersistRows &&
-                rsr::casc_persist_supported(jb.refs))
-                s.choice = kPersist;
+            if (jb.refs->KS4 > 0)
+                s.shape = rows >= rsr::kWideRows ? rsr::mfma_wide_shape() : rsr::mfma_tail_shape();
             p->segs.push_back(s);
             it = p->segs.end() - 1;
         }

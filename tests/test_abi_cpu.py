@@ -21,6 +21,18 @@ def _declared_functions():
     return sorted(set(re.findall(r"\b(rsr_[a-z_0-9]+)\s*\(", text)))
 
 
+def test_binding_constants_match_header():
+    """Every enumerator and #define RSR_* of the header has the same value in
+    the Python binding."""
+    text = open(os.path.join(ROOT, "include", "rsr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    consts = {k: int(v) for k, v in re.findall(r"\b(RSR_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    consts.update({k: int(v) for k, v in re.findall(r"#define\s+(RSR_[A-Z0-9_]+)\s+(\d+)", text)})
+    assert len(consts) >= 20 and consts["RSR_PERSIST"] == 4
+    for name, value in consts.items():
+        assert getattr(A, name) == value, name
+
+
 def test_library_exports_every_declared_symbol():
     lib = A.lib()
     names = _declared_functions()

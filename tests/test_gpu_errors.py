@@ -134,7 +134,14 @@ def test_einval_per_entry_point(rsr_ctx, setup):
     # Requests beyond the build's limits.
     big = np.full((5000, 2), 0.5)
     assert lib.rsr_model_create(h, 5000, 2, big.ctypes.data, ctypes.byref(out)) == A.RSR_EUNSUPPORTED
+    # The persistent cascade takes LABEL mode on consistent rows only.
+    assert lib.rsr_classify(h, refs.h, x, N, A.RSR_COUNT, A.RSR_PERSIST, f, None) == A.RSR_EUNSUPPORTED
+    assert "persistent" in _err(rsr_ctx)
+    both = R.Refs(rsr_ctx, n, 2, np.ones((1, n), np.uint8), np.zeros((1, n), np.uint8))
+    assert not both.consistent
+    assert lib.rsr_classify(h, both.h, x, N, A.RSR_LABEL, A.RSR_PERSIST, f, None) == A.RSR_EUNSUPPORTED
     assert lib.rsr_classify(h, refs.h, x, N, 0, R.RSR_MFMA, f, None) == A.RSR_OK
+    assert lib.rsr_classify(h, refs.h, x, N, A.RSR_LABEL, A.RSR_PERSIST, f, None) == A.RSR_OK
     _check_path_still_exact(rsr_ctx)
 
 
@@ -260,18 +267,17 @@ def test_persistent_barrier_timeout_is_reported(rsr_ctx):
     model = R.Model(rsr_ctx, p)
     xs = R.rsr_sample(rsr_ctx, model, 7, 0, 0, N)
     refs = R.Refs(rsr_ctx, n, 2, sd["lower"], sd["upper"])
-    assert max(refs.R_L, refs.R_U) >= 16_384  # the automatic form is persistent here
     lib = A.lib()
     try:
         assert lib.rsr_debug_barrier_timeout(0) == A.RSR_OK
-        fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO)
+        fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_PERSIST)
         with pytest.raises(R.RSRError) as ei:
             R.rsr_estimate(rsr_ctx, fl, None, N)
         assert ei.value.status == A.RSR_EHIP
         assert "timed out" in str(ei.value)
     finally:
         lib.rsr_debug_barrier_timeout(-1)
-    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO)
+    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_PERSIST)
     est = R.rsr_estimate(rsr_ctx, fl, None, N)
     idx = np.unique(np.concatenate([np.arange(0, N, 211), [N - 1]]))
     x = oracle.sample_at(p, 7, 0, idx.astype(np.uint64))

@@ -84,9 +84,10 @@ FORMS = (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO)
 
 def _classify_both(ctx, cfg, N, lower, upper, level=1):
     """Every kernel form (and the automatic choice, whose LABEL mode on
-    consistent rows is the cascade with FP4 split rounds) in both modes;
-    returns {form: (label flags, count flags, match counts)} and the oracle's
-    answers."""
+    consistent rows is the cascade with FP4 split rounds) in both modes, and
+    the persistent cascade in LABEL mode on consistent rows; returns
+    {form: (label flags, count flags or None, match counts or None)} and the
+    oracle's answers."""
     n, K = cfg["n"], cfg["K"]
     p = cfg["p"]
     m, xs = _sample(ctx, p, cfg["seed"], cfg["stream"], 0, N)
@@ -96,6 +97,9 @@ def _classify_both(ctx, cfg, N, lower, upper, level=1):
         fl = R.rsr_classify(ctx, refs, xs, N, R.RSR_LABEL, form)
         fc, mt = R.rsr_classify(ctx, refs, xs, N, R.RSR_COUNT, form, want_match=True)
         got[form] = (_np(fl), _np(fc), _np(mt).view(np.uint32))
+    if refs.consistent and n * (K - 1) <= 1280:
+        got[R.RSR_PERSIST] = (_np(R.rsr_classify(ctx, refs, xs, N, R.RSR_LABEL, R.RSR_PERSIST)),
+                              None, None)
     x = oracle.sample(p, cfg["seed"], cfg["stream"], 0, N)
     ol, _, _ = oracle.classify(lower, upper, x, mode=0)
     oc, mL, mU = oracle.classify(lower, upper, x, mode=1)
@@ -106,6 +110,8 @@ def _assert_classify(got, want):
     ol, oc, mL, mU = want
     for form, (fl, fc, mt) in got.items():
         np.testing.assert_array_equal(fl, ol, err_msg=f"label flags, form {form}")
+        if fc is None:
+            continue
         np.testing.assert_array_equal(fc, oc, err_msg=f"count flags, form {form}")
         np.testing.assert_array_equal(mt[:, 0], mL, err_msg=f"lower matches, form {form}")
         np.testing.assert_array_equal(mt[:, 1], mU, err_msg=f"upper matches, form {form}")
@@ -374,10 +380,11 @@ def test_cascade_fp4_split_rounds_large_rows(rsr_ctx):
 
 def test_persistent_cascade_long_rows(rsr_ctx):
     """2.2e4 path and cut rows of the 647-edge graph (21 words per row): the
-    automatic LABEL form runs the persistent cascade (round 0 on the vector
-    ALU, the later rounds in one cooperative launch, compacted through
-    per-block regions).  A ragged N; labels equal the oracle's and the
-    popcount cascade's, and a second call on the same buffers repeats them."""
+    persistent cascade (round 0 on the vector ALU, the later rounds in one
+    cooperative launch, compacted through per-block regions) and the
+    automatic LABEL form (round kernels with growth 8 at this many rows).  A
+    ragged N; labels equal the oracle's and the popcount cascade's, and a
+    second call on the same buffers repeats them."""
     cfg = WL.configs.batched(n_scen=1, N=1, graphs=[5], ref_scale=1.0)
     sys_ = cfg["systems"][0]
     n = sys_["n"]
@@ -386,14 +393,15 @@ def test_persistent_cascade_long_rows(rsr_ctx):
     m, xs = _sample(rsr_ctx, p, 5, 0, 0, N)
     refs = R.Refs(rsr_ctx, n, 2, sys_["lower"], sys_["upper"])
     assert refs.consistent and max(refs.R_L, refs.R_U) >= 16_384
-    auto = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO)
-    first = _np(auto).copy()
-    R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_AUTO, flags=auto)
-    pop = _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT))
     x = oracle.sample(p, 5, 0, 0, N)
     want, _, _ = oracle.classify(sys_["lower"], sys_["upper"], x, mode=0)
-    np.testing.assert_array_equal(first, want)
-    np.testing.assert_array_equal(_np(auto), want)
+    for form in (R.RSR_PERSIST, R.RSR_AUTO):
+        fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
+        first = _np(fl).copy()
+        R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form, flags=fl)
+        np.testing.assert_array_equal(first, want, err_msg=f"form {form}")
+        np.testing.assert_array_equal(_np(fl), want, err_msg=f"form {form}, second call")
+    pop = _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_POPCOUNT))
     np.testing.assert_array_equal(pop, want)
 
 
@@ -510,8 +518,9 @@ def test_eval_all_graph_sizes(rsr_ctx, g_idx, level):
 def test_classify_forms_agree_every_width(rsr_ctx, g):
     """The eight batched graphs (120 to 1250 edges: 4 to 40 packed words, 2 to
     20 FP4 k-steps of 64) with 5 % of their reference rows: every form gives
-    the popcount form's COUNT flags and match counts and its LABEL flags, on a
-    ragged N; the oracle checks sampled indices."""
+    the popcount form's COUNT flags and match counts and its LABEL flags (the
+    persistent cascade its LABEL flags), on a ragged N; the oracle checks
+    sampled indices."""
     cfg = WL.configs.batched(n_scen=1, N=1, graphs=[g], ref_scale=0.05)
     sd = cfg["systems"][0]
     n, p = sd["n"], cfg["jobs"][0]["p"]
@@ -527,6 +536,9 @@ def test_classify_forms_agree_every_width(rsr_ctx, g):
         np.testing.assert_array_equal(_np(mt).view(np.uint32), mt0, err_msg=f"counts, form {form}")
         fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
         np.testing.assert_array_equal(_np(fl), fl0, err_msg=f"LABEL flags, form {form}")
+    assert refs.consistent
+    fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, R.RSR_PERSIST)
+    np.testing.assert_array_equal(_np(fl), fl0, err_msg="LABEL flags, persistent cascade")
     idx = np.unique(np.concatenate([np.arange(0, N, 97), [N - 1]]))
     x = oracle.sample_at(p, 11, 0, idx.astype(np.uint64))
     oc, mL, mU = oracle.classify(sd["lower"], sd["upper"], x, mode=1)
