@@ -98,8 +98,10 @@ typedef struct {
  * n_edges = n.
  *   RSR_SYS_ST_CONNECTIVITY: Phi = 1 when sink is reachable from source over
  *     edges whose state is at least `level` (1 <= level <= K-1), else 0:
- *     single-OD connectivity for K = 2, and the level-`level` bottleneck
- *     system for K > 2 (section 4.1).
+ *     single-OD connectivity for K = 2 (section 4.1), and for K > 2 the
+ *     level-`level` bottleneck system, one target state of section 3.5's
+ *     multi-state workflow (the paper fixes no multi-state s-t function;
+ *     this one is coherent in every component).
  *   RSR_SYS_GLOBAL_CONNECTIVITY: edges work when their state is at least 1;
  *     the system state is 0 when some node is cut off from the rest, 1 when
  *     the working edges connect every node but some single edge failure

@@ -230,7 +230,9 @@ int64_t or_paper_violation(int n, int M, const uint8_t* x, const uint8_t* r, int
 /* Components are the undirected edges of a graph; an edge is usable when its
  * state is at least `level`.  Phi = 1 when t is reachable from s over usable
  * edges (the single-OD connectivity of section 4.1; for K > 2 the level gives
- * the coherent bottleneck system S >= level).  Plain queue BFS over an edge
+ * the coherent bottleneck system S >= level, one target state of the
+ * multi-state workflow of section 3.5, a reading: the paper fixes no
+ * multi-state s-t function).  Plain queue BFS over an edge
  * list; adjacency is rebuilt on every call. */
 int or_phi_st(int n_nodes, int n_edges, const int32_t* eu, const int32_t* ev, int s, int t,
               int level, const uint8_t* x) {

@@ -1,0 +1,96 @@
+"""GPU property tests on random coherent systems: s-t connectivity of random
+multigraphs with K = 2 or 3 states at every level, random state
+probabilities, random subsets of the complete reference sets (either side
+may be empty) and a random sample count.  Through the C ABI, the whole
+Stage-2 path (sample, LABEL classify, evaluate the unclassified samples,
+estimate, gradient) equals the oracle: flags, Y and counts exactly, the
+estimate bit for bit, the gradient within 1e-5 relative; COUNT mode in
+every form gives the oracle's flags and match counts, and LABEL mode in
+every form (the persistent cascade included) its flags."""
+import numpy as np
+import pytest
+import torch
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+import paper_2604_17066_amd as R
+from strategies import st_systems
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-5
+SETTINGS = settings(max_examples=60, deadline=None, derandomize=True, database=None,
+                    suppress_health_check=[HealthCheck.too_slow, HealthCheck.filter_too_much])
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _refs(graph, K, level, seed, keep_l, keep_u):
+    n = graph["edge_u"].size
+    table = oracle.phi_table_st(graph, K=K, level=level)
+    lo, up = oracle.reference_sets(table, n, K, level=1)
+    rng = np.random.default_rng(seed + 1)
+    lo = np.ascontiguousarray(lo[rng.random(len(lo)) < keep_l])
+    up = np.ascontiguousarray(up[rng.random(len(up)) < keep_u])
+    return lo, up
+
+
+@SETTINGS
+@given(st_systems(), st.floats(0.0, 1.0), st.floats(0.0, 1.0), st.integers(1, 5000))
+def test_random_systems_full_path(rsr_ctx, sysd, keep_l, keep_u, N):
+    graph, K, level, p, seed = sysd
+    n = graph["edge_u"].size
+    lo, up = _refs(graph, K, level, seed, keep_l, keep_u)
+    print(f"K={K} level={level} n={n} rows={len(lo)}+{len(up)} N={N} seed={seed}", flush=True)
+    m = R.Model(rsr_ctx, p)
+    refs = R.Refs(rsr_ctx, n, K, lo, up)
+    sysm = R.System(rsr_ctx, graph, K=K, level=level)
+    est, buf = R.stage2(rsr_ctx, m, refs, sysm, N, seed, stream_id=5)
+    G, counts = R.rsr_grad(rsr_ctx, m, buf.samples, buf.Y, N, want_counts=True)
+    x = oracle.sample(p, seed, 5, 0, N)
+    fl, _, _ = oracle.classify(lo, up, x, mode=0)
+    Y, nev = oracle.eval_unknown(graph, x, fl, which=0, level=level)
+    cnt = oracle.counts(fl, Y)
+    oest = oracle.estimate(cnt)
+    c, Gref = oracle.grad(p, x, Y)
+    np.testing.assert_array_equal(_np(buf.flags), fl)
+    np.testing.assert_array_equal(_np(buf.Y), Y)
+    assert int(_np(buf.n_eval)[0]) == nev
+    for k, name in enumerate(oracle.COUNT_NAMES):
+        assert est[name] == int(cnt[k]), name
+    for k, name in enumerate(oracle.EST_NAMES):
+        assert est[name] == oest[k] or (np.isinf(est[name]) and np.isinf(oest[k])), name
+    np.testing.assert_array_equal(_np(counts).view(np.uint64), c)
+    G = _np(G).astype(np.float64)
+    nz = Gref != 0
+    assert np.all(np.abs(G[nz] - Gref[nz]) <= GRAD_RTOL * np.abs(Gref[nz]))
+    assert np.all(G[~nz] == 0.0)
+
+
+@SETTINGS
+@given(st_systems(min_edges=6), st.floats(0.0, 1.0), st.floats(0.0, 1.0), st.integers(1, 5000))
+def test_random_systems_every_form(rsr_ctx, sysd, keep_l, keep_u, N):
+    graph, K, level, p, seed = sysd
+    n = graph["edge_u"].size
+    lo, up = _refs(graph, K, level, seed, keep_l, keep_u)
+    print(f"K={K} level={level} n={n} rows={len(lo)}+{len(up)} N={N} seed={seed}", flush=True)
+    m = R.Model(rsr_ctx, p)
+    refs = R.Refs(rsr_ctx, n, K, lo, up)
+    assert refs.consistent
+    xs = R.rsr_sample(rsr_ctx, m, seed, 0, 0, N)
+    x = oracle.sample(p, seed, 0, 0, N)
+    ol, _, _ = oracle.classify(lo, up, x, mode=0)
+    oc, mL, mU = oracle.classify(lo, up, x, mode=1)
+    for form in (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO):
+        fc, mt = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, form, want_match=True)
+        mt = _np(mt).view(np.uint32)
+        np.testing.assert_array_equal(_np(fc), oc, err_msg=f"COUNT flags, form {form}")
+        np.testing.assert_array_equal(mt[:, 0], mL, err_msg=f"lower matches, form {form}")
+        np.testing.assert_array_equal(mt[:, 1], mU, err_msg=f"upper matches, form {form}")
+    for form in (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO, R.RSR_PERSIST):
+        fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
+        np.testing.assert_array_equal(_np(fl), ol, err_msg=f"LABEL flags, form {form}")

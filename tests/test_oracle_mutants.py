@@ -80,7 +80,7 @@ MUTANTS = {
     "flow: one augmenting path only": ("        total += push;\n    }", "        total += push;\n        break;\n    }"),
 }
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_boundary.py", "test_oracle_global.py",
-             "test_oracle_flow.py"]
+             "test_oracle_flow.py", "test_oracle_properties.py"]
 
 
 def _run(name, old, new, tmp):
