@@ -54,7 +54,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", default="auto", choices=["auto", "popcount", "mfma", "mfma_fp4", "persist"])
+    ap.add_argument("--form", default="auto", choices=["auto", "popcount", "mfma", "mfma_fp4", "persist"],
+                    help="classification form of the graph2 step and of the multi-state leg")
     ap.add_argument("--skip-legs", action="store_true",
                     help="only the graph2 step (no scaling / multi-state / batched legs)")
     ap.add_argument("--only-legs", default="", metavar="LIST",
@@ -81,7 +82,9 @@ def main():
     if args.only_legs:
         import paper_2604_17066_amd as R
         ctx = R.Context(0)
-        runs = {"scaling": lambda: scaling_leg(ctx, 5), "multi": lambda: multi_leg(ctx, 5),
+        form = {"auto": R.RSR_AUTO, "popcount": R.RSR_POPCOUNT, "mfma": R.RSR_MFMA,
+                "mfma_fp4": R.RSR_MFMA_FP4, "persist": R.RSR_PERSIST}[args.form]
+        runs = {"scaling": lambda: scaling_leg(ctx, 5), "multi": lambda: multi_leg(ctx, 5, form),
                 "batched": lambda: batched_leg(ctx, args.batched_scale, args.batched_reps,
                                                tuple(int(float(v)) for v in args.batched_n.split(","))),
                 "stage1": lambda: stage1_leg(ctx, False), "global": lambda: global_leg(ctx),
@@ -299,7 +302,7 @@ def main():
     if not args.skip_legs:
         extra["scaling_count_mode"] = scaling_leg(
             ctx, reps, None if args.no_cpu_baseline else args.cpu_seconds)
-        extra["multi_state"] = multi_leg(ctx, reps)
+        extra["multi_state"] = multi_leg(ctx, reps, form)
         extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps,
                                                 tuple(int(float(v)) for v in args.batched_n.split(",")))
         extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
@@ -408,11 +411,13 @@ def scaling_leg(ctx, reps, cpu_seconds=None):
     return out
 
 
-def multi_leg(ctx, reps):
+def multi_leg(ctx, reps, form=None):
     """Three-state edges on graph2, bottleneck levels 1 and 2 (5e4 rows per
     level), N = 1e6: P(S >= 1), P(S >= 2), the PMF by differences and the fp32
-    gradients, full path per level."""
+    gradients, full path per level, classified in `form` (default: the
+    automatic form)."""
     import paper_2604_17066_amd as R
+    form = R.RSR_AUTO if form is None else form
     import workloads as WL
     cfg = WL.configs.multi()
     N, n, K = cfg["N"], cfg["n"], cfg["K"]
@@ -428,7 +433,7 @@ def multi_leg(ctx, reps):
     def one_pass():
         ests = {}
         for k, (refs, system) in levels.items():
-            ests[k], _ = R.stage2(ctx, model, refs, system, N, cfg["seed"], buffers=buf)
+            ests[k], _ = R.stage2(ctx, model, refs, system, N, cfg["seed"], form=form, buffers=buf)
         return ests
     ests = one_pass()
     import time as _t
@@ -441,7 +446,7 @@ def multi_leg(ctx, reps):
     ms = (_t.perf_counter() - t0) * 1e3 / reps
     P1, P2 = ests[1]["P"], ests[2]["P"]
     res = {"workload": "graph2 with states {0,1,2}, levels 1 and 2, 5e4 rows per level, N=1e6",
-           "ms_both_levels": ms, "P_ge1": P1, "P_ge2": P2,
+           "form": int(form), "ms_both_levels": ms, "P_ge1": P1, "P_ge2": P2,
            "pmf": [1.0 - P1, P1 - P2, P2], "p_u": [ests[1]["p_u"], ests[2]["p_u"]],
            "tests_per_s": float(N) * sum(r.R_L + r.R_U for r, _ in levels.values()) / (ms * 1e-3)}
     log(f"multi-state: {ms:.2f} ms for both levels, P(S>=1)={P1:.5f} P(S>=2)={P2:.5f}")

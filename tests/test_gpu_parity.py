@@ -130,6 +130,34 @@ def test_refs_consistency_flag(rsr_ctx):
     assert R.Refs(rsr_ctx, n, 2, lower[:0], upper).consistent
 
 
+@pytest.mark.parametrize("name", ["graph2", "multi"])
+def test_refs_consistency_large_sets(rsr_ctx, name):
+    """The consistency check over thousands of rows per side (in the FP4 form
+    when the handle has matrix-core operands): the structural sets are
+    consistent, one upper row appended anywhere below a lower row (equal to
+    the last lower row, or a lower row with working components removed) makes
+    them inconsistent, and an all-working upper row keeps them consistent."""
+    if name == "graph2":
+        cfg = WL.configs.graph2(N=1)
+        n, K = cfg["n"], 2
+        lower, upper = cfg["lower"][:3000], cfg["upper"][:2500]
+    else:
+        cfg = WL.configs.multi(N=1, R_per_level=4000)
+        n, K = cfg["n"], 3
+        lower, upper = cfg["levels"][2]["lower"], cfg["levels"][2]["upper"]
+    assert R.Refs(rsr_ctx, n, K, lower, upper).consistent
+    rng = np.random.default_rng(3)
+    below = lower[len(lower) // 2].copy()
+    on = np.nonzero(below)[0]
+    below[rng.choice(on, size=len(on) // 3, replace=False)] = 0
+    for extra in (lower[-1:], below[None, :]):
+        bad = np.concatenate([upper, extra])
+        assert not R.Refs(rsr_ctx, n, K, lower, bad).consistent
+        assert not R.Refs(rsr_ctx, n, K, lower, bad[::-1]).consistent
+    top = np.full((1, n), K - 1, np.uint8)
+    assert R.Refs(rsr_ctx, n, K, lower, np.concatenate([upper, top])).consistent
+
+
 def test_classify_tiny_complete_refs(rsr_ctx):
     cfg = WL.configs.tiny(N=100_000)
     got, want, _ = _classify_both(rsr_ctx, cfg, cfg["N"], cfg["lower"], cfg["upper"])
