@@ -387,7 +387,8 @@ typedef struct {
 /* Builds a plan for n_jobs jobs: chooses a kernel configuration per job shape,
  * orders the work, and records every launch of every job into one HIP graph.
  * The configuration of a segment (the jobs sharing a reference set and a
- * system) is chosen by timing candidates on its own samples, with results
+ * system) is chosen by timing candidates on its own samples (its first jobs,
+ * at least 2^22 samples, or all of them when it has fewer), with results
  * kept in a tuning cache:
  *   tune_cache NULL:  no timing; every segment takes the default
  *                     configuration (the automatic classification form);
@@ -400,7 +401,9 @@ typedef struct {
  *                     per job, 3 FP4 per job, 4 persistent cascade;
  *                     "first", "growth", "split": the cascade's round
  *                     rows; "tail": 0 popcount rounds, 1 FP4 rounds after
- *                     round 0, 2 FP4 rounds from round 0 on; "ms"}.
+ *                     round 0, 2 FP4 rounds from round 0 on; "ms": the
+ *                     segment's classification time, timed on those
+ *                     samples and scaled to all of them}.
  *                     Segments whose key is present take the stored choice
  *                     without timing; the others are timed, and the file is
  *                     rewritten (via a temporary file and a rename) with the

@@ -204,12 +204,15 @@ rsr_status phip(rsr_ctx* ctx, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return phip(ctx, e_, #call);   \
     } while (0)
 
-rsr::SegSrc seg_src(const rsr_plan* p, const Segment& s, int si) {
+// The segment's jobs as one sample range; a prefix (n_jobs > 0) takes its
+// first n_jobs jobs (device order), `total` samples.
+rsr::SegSrc seg_src(const rsr_plan* p, const Segment& s, int si, int n_jobs = 0,
+                    int64_t total = 0) {
     rsr::SegSrc src{};
     src.jobs = p->d_jobs + s.first_pos;
     src.offsets = p->d_offsets + p->offset_base[si];
-    src.n_jobs = static_cast<int32_t>(s.jobs.size());
-    src.total = s.total;
+    src.n_jobs = static_cast<int32_t>(n_jobs > 0 ? n_jobs : s.jobs.size());
+    src.total = n_jobs > 0 ? total : s.total;
     return src;
 }
 
@@ -234,9 +237,12 @@ hipError_t enqueue_sample(const rsr_plan* p, int si, hipStream_t st) {
                                    static_cast<int>(s.jobs.size()), s.total, p->ctx->cu_count * 16);
 }
 
+// Classification of the segment, or of its first n_jobs jobs (`total`
+// samples) when n_jobs > 0.
 hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice choice,
-                            const rsr::CascadeShape& shape) {
+                            const rsr::CascadeShape& shape, int n_jobs = 0, int64_t total = 0) {
     const Segment& s = p->segs[si];
+    const rsr::SegSrc src = seg_src(p, s, si, n_jobs, total);
     if (choice == kPersist) {
         // counters[15] is the barrier time-out flag, cleared once per run at
         // the start of the graph and copied back with the counts.
@@ -244,7 +250,7 @@ hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice ch
         hipError_t e = rsr::launch_fill_u64(st, reinterpret_cast<uint64_t*>(p->d_casc_state),
                                             (p->casc_state_words + 1) / 2, 0);
         if (e != hipSuccess) return e;
-        return rsr::launch_casc_persist(st, s.refs, seg_src(p, s, si), cb, rsr::mfma_head_shape(),
+        return rsr::launch_casc_persist(st, s.refs, src, cb, rsr::mfma_head_shape(),
                                         p->d_casc_state,
                                         reinterpret_cast<unsigned long long*>(p->d_casc_counters + 15),
                                         p->ctx->cu_count);
@@ -253,11 +259,10 @@ hipError_t enqueue_classify(const rsr_plan* p, int si, hipStream_t st, Choice ch
         const rsr::CascadeBuffers cb = casc_buffers(p);
         hipError_t e = rsr::launch_fill_u64(st, cb.counters, rsr::CascadeBuffers::kMaxRounds, 0);
         if (e != hipSuccess) return e;
-        return rsr::launch_dom_cascade(st, s.refs, seg_src(p, s, si), cb, shape,
-                                       p->ctx->cu_count * 8);
+        return rsr::launch_dom_cascade(st, s.refs, src, cb, shape, p->ctx->cu_count * 8);
     }
-    for (int j : s.jobs) {
-        const rsr_job& jb = p->jobs[j];
+    for (int k = 0; k < src.n_jobs; ++k) {
+        const rsr_job& jb = p->jobs[s.jobs[k]];
         hipError_t e = choice == kMfmaPerJob || choice == kMfma4PerJob
                            ? rsr::launch_dom_mfma(st, s.refs, jb.d_samples, jb.N, RSR_LABEL,
                                                   choice == kMfma4PerJob, p->ctx->cu_count,
@@ -340,10 +345,19 @@ rsr_status write_cache(rsr_ctx* ctx, const std::string& path,
     return RSR_OK;
 }
 
+// Samples on which tuning times its candidates: the first jobs of a segment
+// up to at least this many (every job when the segment has fewer).  The best
+// configuration depends on how the samples are classified, not on how many
+// jobs share the launch, and a whole segment can take half a second per
+// trial (64 jobs of 1e6 samples on the 1250-edge graph).
+constexpr int64_t kTuneSamples = int64_t{1} << 22;
+
 // Times candidate classifications of one segment on its own samples (drawn
-// once) and keeps the fastest.  For a consistent reference set the split-round
-// form (popcount or FP4) is chosen first on the default cascade shape, then
-// the shape with that form; otherwise the per-job forms are compared.
+// once, the trials on a prefix of kTuneSamples) and keeps the fastest; the
+// segment's time is the prefix's scaled by the sample counts.  For a
+// consistent reference set the split-round form (popcount or FP4) is chosen
+// first on the default cascade shape, then the shape with that form;
+// otherwise the per-job forms are compared.
 rsr_status tune_segment(rsr_plan* p, int si) {
     Segment& s = p->segs[si];
     rsr_ctx* ctx = p->ctx;
@@ -351,6 +365,11 @@ rsr_status tune_segment(rsr_plan* p, int si) {
         Choice c;
         rsr::CascadeShape shape;
     };
+    int n_tune = 0;
+    int64_t tune_total = 0;
+    while (n_tune < static_cast<int>(s.jobs.size()) && tune_total < kTuneSamples)
+        tune_total += p->jobs[s.jobs[n_tune++]].N;
+    const float scale = static_cast<float>(static_cast<double>(s.total) / static_cast<double>(tune_total));
     PLAN_HIP(ctx, enqueue_sample(p, si, p->cap));
     hipEvent_t a, b;
     PLAN_HIP(ctx, hipEventCreate(&a));
@@ -358,10 +377,10 @@ rsr_status tune_segment(rsr_plan* p, int si) {
     float best = 1e30f;
     auto trial = [&](const std::vector<Cand>& cands) -> rsr_status {
         for (const Cand& c : cands) {
-            PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));  // warm-up
+            PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape, n_tune, tune_total));  // warm-up
             PLAN_HIP(ctx, hipEventRecord(a, p->cap));
             for (int rep = 0; rep < 2; ++rep)
-                PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape));
+                PLAN_HIP(ctx, enqueue_classify(p, si, p->cap, c.c, c.shape, n_tune, tune_total));
             PLAN_HIP(ctx, hipEventRecord(b, p->cap));
             PLAN_HIP(ctx, hipEventSynchronize(b));
             float ms = 0.0f;
@@ -387,7 +406,7 @@ rsr_status tune_segment(rsr_plan* p, int si) {
         st = trial(forms);
         // The persistent cascade keeps its own round sizes.
         if (st != RSR_OK || s.choice == kPersist) {
-            s.tuned_ms = best / 2.0f;
+            s.tuned_ms = best / 2.0f * scale;
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
             return st;
@@ -409,7 +428,7 @@ rsr_status tune_segment(rsr_plan* p, int si) {
         if (s.refs->KS4 > 0) forms.push_back({kMfma4PerJob, rsr::CascadeShape{}});
         st = trial(forms);
     }
-    s.tuned_ms = best / 2.0f;
+    s.tuned_ms = best / 2.0f * scale;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return st;

@@ -178,8 +178,8 @@ def test_plan_tuning_cache(rsr_ctx, tmp_path):
 
 
 @pytest.mark.parametrize("choice,tail,first,growth,split", [(0, 0, 16, 4, 64), (0, 1, 16, 6, 256),
-                                                            (0, 2, 32, 4, 64), (0, 2, 32, 8, 256),
-                                                            (4, 2, 32, 6, 256)])
+                                                            (0, 1, 16, 8, 512), (0, 2, 32, 4, 64),
+                                                            (0, 2, 32, 8, 256), (4, 2, 32, 6, 256)])
 def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, growth, split):
     """Every cascade a tuning cache can name (popcount rounds, matrix-core
     rounds after round 0, matrix-core rounds from round 0 on, the persistent
@@ -206,6 +206,29 @@ def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, grow
             np.testing.assert_array_equal(_np(b.flags), _np(pb.flags), err_msg=f"job {k} run {rep}")
             np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k} run {rep}")
             assert est[k]["P"] == pe["P"] and est[k]["n_u"] == pe["n_u"], (k, rep)
+    plan.close()
+
+
+def test_plan_tuning_on_a_job_prefix(rsr_ctx, tmp_path):
+    """A segment of six jobs of 1e6 samples: tuning times its candidates on
+    the first five (the first jobs reaching 2^22 samples) and stores a
+    positive time for the segment; the tuned plan gives the plain path's
+    flags, Y and estimates for every job, the one tuning did not time
+    included."""
+    import json
+    path = tmp_path / "tune.json"
+    jobs, systems = _small_batch(rsr_ctx, n_scen=6, graphs=(1,), Ns=(1_000_000,))
+    plan = R.Plan(rsr_ctx, jobs, tune=str(path))
+    entries = json.loads(path.read_text())
+    assert len(entries) == 1 and all(e["ms"] > 0 for e in entries.values())
+    plan.run()
+    est, _ = plan.results()
+    for k, jb in enumerate(jobs):
+        pe, pb = _plain(rsr_ctx, jb)
+        b = jb["buffers"]
+        np.testing.assert_array_equal(_np(b.flags), _np(pb.flags), err_msg=f"job {k}")
+        np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k}")
+        assert est[k]["P"] == pe["P"] and est[k]["n_u"] == pe["n_u"], k
     plan.close()
 
 
