@@ -302,9 +302,11 @@ def main():
     if not args.skip_legs:
         extra["scaling_count_mode"] = scaling_leg(
             ctx, reps, None if args.no_cpu_baseline else args.cpu_seconds)
-        extra["multi_state"] = multi_leg(ctx, reps, form)
+        cpu_s = None if args.no_cpu_baseline else args.cpu_seconds
+        extra["multi_state"] = multi_leg(ctx, reps, form, cpu_s)
         extra["batched_vs_plain"] = batched_leg(ctx, args.batched_scale, args.batched_reps,
-                                                tuple(int(float(v)) for v in args.batched_n.split(",")))
+                                                tuple(int(float(v)) for v in args.batched_n.split(",")),
+                                                cpu_s)
         extra["stage1"] = stage1_leg(ctx, not args.no_cpu_baseline)
         extra["global_connectivity"] = global_leg(ctx)
         extra["max_flow"] = flow_leg(ctx)
@@ -411,11 +413,12 @@ def scaling_leg(ctx, reps, cpu_seconds=None):
     return out
 
 
-def multi_leg(ctx, reps, form=None):
+def multi_leg(ctx, reps, form=None, cpu_seconds=None):
     """Three-state edges on graph2, bottleneck levels 1 and 2 (5e4 rows per
     level), N = 1e6: P(S >= 1), P(S >= 2), the PMF by differences and the fp32
     gradients, full path per level, classified in `form` (default: the
-    automatic form)."""
+    automatic form).  With cpu_seconds, also the oracle's baseline on the
+    first samples (cpu_baseline_multi)."""
     import paper_2604_17066_amd as R
     form = R.RSR_AUTO if form is None else form
     import workloads as WL
@@ -450,6 +453,8 @@ def multi_leg(ctx, reps, form=None):
            "pmf": [1.0 - P1, P1 - P2, P2], "p_u": [ests[1]["p_u"], ests[2]["p_u"]],
            "tests_per_s": float(N) * sum(r.R_L + r.R_U for r, _ in levels.values()) / (ms * 1e-3)}
     log(f"multi-state: {ms:.2f} ms for both levels, P(S>=1)={P1:.5f} P(S>=2)={P2:.5f}")
+    if cpu_seconds:
+        res["cpu_baseline"] = cpu_baseline_multi(ctx, cfg, model, levels, buf, form, cpu_seconds)
     return res
 
 
@@ -613,14 +618,16 @@ def flow_leg(ctx):
     return out
 
 
-def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000)):
+def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000), cpu_seconds=None):
     """64 hazard scenarios x 8 graphs = 512 jobs, at N = 2^18 (SE <= 9.8e-4 <
     1e-3 for any P) and at N = 1e6: P_sys and the gradient of every job by the
     batched plan (one graph launch, tuned configurations) against the plain
     form (the library's calls job by job, with a host synchronisation per job
     for its estimate), in the library's default (automatic) form and, for
     reference, in the popcount form.  Plan creation is timed with an empty
-    tuning cache and again with the cache it wrote."""
+    tuning cache and again with the cache it wrote.  With cpu_seconds, also
+    the oracle's baseline on the first samples of one job per graph
+    (cpu_baseline_batched, against the plan's outputs at the first N)."""
     import tempfile
     import time as _t
     import torch
@@ -703,6 +710,8 @@ def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000)):
                         "plan_create_s": create_s, "plan_create_from_cache_s": create_cached_s,
                         "identical_estimates": same, "max_se": se, "tuned_segments": choices,
                         "nominal_tests_per_s_batched": total_tests / (batched_ms * 1e-3)}
+        if cpu_seconds and N == Ns[0]:
+            out["cpu_baseline"] = cpu_baseline_batched(cfg, jobs, cpu_seconds)
         del jobs
         torch.cuda.empty_cache()
     return out
@@ -719,6 +728,113 @@ def cpu_baseline_boundary(cfg, seed, count):
     dt = time.perf_counter() - t
     return {"value": count / dt, "unit": "boundary searches/s", "cores": oracle.get_threads(),
             "kind": "oracle", "sample": f"{count} start samples of graph2, {dt:.2f} s"}
+
+
+def _fit_to_budget(run, seconds, n0, cap):
+    """Runs run(n) (returning (time, result)) on growing sample counts from n0
+    until one takes at least a quarter of `seconds` or reaches `cap` samples,
+    so that fixed per-call costs do not inflate the per-sample time; returns
+    (n, time, result) of the last run."""
+    n = min(n0, cap)
+    t, res = run(n)
+    while t < 0.25 * seconds and n < cap:
+        n = min(cap, int(n * min(16.0, max(2.0, 0.6 * seconds / max(t, 1e-6)))))
+        t, res = run(n)
+    return n, t, res
+
+
+def cpu_baseline_multi(ctx, cfg, model, levels, buf, form, seconds):
+    """The oracle's whole hot path (sample, classify, evaluate, estimate,
+    gradient) for both levels of the multi-state workload on its first
+    samples, sized to about `seconds` (_fit_to_budget); the time of all 1e6
+    samples is a linear extrapolation.  The GPU's flags and Y for those samples, at
+    each level, are compared with the oracle's."""
+    import numpy as np
+    import oracle
+    import torch
+    import paper_2604_17066_amd as R
+    cores = oracle.get_threads()
+
+    def run(n_sub):
+        t = time.perf_counter()
+        x = oracle.sample(cfg["p"], cfg["seed"], 0, 0, n_sub)
+        out = {}
+        for k in (1, 2):
+            lv = cfg["levels"][k]
+            fl, _, _ = oracle.classify(lv["lower"], lv["upper"], x, mode=0)
+            Y, _ = oracle.eval_unknown(cfg["graph"], x, fl, which=0, level=k)
+            oracle.estimate(oracle.counts(fl, Y))
+            oracle.grad(cfg["p"], x, Y)
+            out[k] = (fl, Y)
+        return time.perf_counter() - t, out
+
+    n_sub, t, res = _fit_to_budget(run, seconds, 1024, cfg["N"])
+    same = True
+    for k, (refs, system) in levels.items():
+        R.stage2(ctx, model, refs, system, cfg["N"], cfg["seed"], form=form, buffers=buf)
+        torch.cuda.synchronize()
+        same = same and np.array_equal(buf.flags[:n_sub].cpu().numpy(), res[k][0]) and \
+            np.array_equal(buf.Y[:n_sub].cpu().numpy(), res[k][1])
+    full = t * cfg["N"] / n_sub
+    log(f"cpu oracle, multi-state: {n_sub} samples x 2 levels in {t:.2f}s on {cores} threads "
+        f"(flags and Y equal the GPU's: {same})")
+    return {"value": n_sub / t, "unit": "samples/s (both levels, whole hot path)", "cores": cores,
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"first {n_sub} of the {cfg['N']} samples, both levels, sample + classify + "
+                      f"evaluate + estimate + gradient, {t:.1f} s; the full workload's time is "
+                      f"extrapolated linearly: {full:.0f} s",
+            "extrapolated_full_s": full, "gpu_flags_and_Y_equal": bool(same)}
+
+
+def cpu_baseline_batched(cfg, jobs, seconds):
+    """The oracle's whole hot path on the first samples of the first job of
+    each graph (one hazard scenario per graph), sized to about `seconds` in
+    all (_fit_to_budget per graph); the time of all 512 jobs at each N is
+    extrapolated linearly per graph.  The plan's flags and Y for those samples are
+    compared with the oracle's."""
+    import numpy as np
+    import oracle
+    import torch
+    cores = oracle.get_threads()
+    first = {}
+    for k, jd in enumerate(cfg["jobs"]):
+        first.setdefault(jd["system"], k)
+    per_graph = {g: sum(1 for jd in cfg["jobs"] if jd["system"] == g) for g in first}
+
+    def run(g, n_sub):
+        sd, jd = cfg["systems"][g], cfg["jobs"][first[g]]
+        t = time.perf_counter()
+        x = oracle.sample(jd["p"], jd["seed"], 0, 0, n_sub)
+        fl, _, _ = oracle.classify(sd["lower"], sd["upper"], x, mode=0)
+        Y, _ = oracle.eval_unknown(sd["graph"], x, fl)
+        oracle.estimate(oracle.counts(fl, Y))
+        oracle.grad(jd["p"], x, Y)
+        return time.perf_counter() - t, (fl, Y)
+
+    share = seconds / len(first)
+    rate, same, n_used, t_used = {}, True, 0, 0.0
+    torch.cuda.synchronize()
+    for g in first:
+        n_sub, t, (fl, Y) = _fit_to_budget(lambda n: run(g, n), share, 256, jobs[first[g]]["N"])
+        rate[g] = t / n_sub
+        n_used += n_sub
+        t_used += t
+        b = jobs[first[g]]["buffers"]
+        same = same and np.array_equal(b.flags[:n_sub].cpu().numpy(), fl) and \
+            np.array_equal(b.Y[:n_sub].cpu().numpy(), Y)
+    full = {f"N{N}": sum(rate[g] * per_graph[g] * N for g in first) for N in (1 << 18, 1_000_000)}
+    log(f"cpu oracle, batched: {n_used} samples over {len(first)} graphs in {t_used:.2f}s on "
+        f"{cores} threads (flags and Y equal the plan's: {same}); all {len(cfg['jobs'])} jobs "
+        f"extrapolated: "
+        + ", ".join(f"{k} {v:.0f} s" for k, v in full.items()))
+    return {"value": n_used / t_used,
+            "unit": f"samples/s (mix of the {len(first)} graphs, whole hot path)",
+            "cores": cores, "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"first samples of one hazard scenario per graph ({n_used} in all, about "
+                      f"{share:.1f} s per graph), sample + classify + evaluate + estimate + "
+                      f"gradient, {t_used:.1f} s; the time of all {len(cfg['jobs'])} jobs is "
+                      f"extrapolated linearly per graph",
+            "extrapolated_full_s": full, "plan_flags_and_Y_equal": bool(same)}
 
 
 def _cpu_model():
