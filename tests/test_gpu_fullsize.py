@@ -2,10 +2,11 @@
 
 * Multi-state workload (295 three-state edges, 5e4 reference rows per
   level, N = 1e6): every Y of both levels equals the oracle's plain Monte
-  Carlo, flags on sampled indices equal the oracle's Algorithm 1 (the
-  automatic LABEL cascade runs a round of 17 280 rows per side here, above
-  the 64-chunk cap of 16 384 rows, so chunks hold more than 256 rows), P is
-  bit-exact and the fp32 gradient is within 1e-5 of the fp64 oracle.
+  Carlo, flags on sampled indices equal the oracle's Algorithm 1, P is
+  bit-exact and the fp32 gradient is within 1e-5 of the fp64 oracle.  The
+  LABEL flags of the popcount cascade (whose round over rows 4 000..20 000
+  wants 125 chunks of 128 rows and is held to the cap of 64 chunks) and of
+  the persistent cascade equal the automatic form's on every sample.
 * One job of the batched workload at its full reference-set size (the
   647-edge graph, 2.2e4 + 2.2e4 rows) inside a plan, against the oracle.
 """
@@ -53,6 +54,10 @@ def test_multistate_config_size(rsr_ctx):
         np.testing.assert_array_equal(unpack_states(_np(buf.samples)[:, idx], n, K), x[idx])
         fl, _, _ = oracle.classify(lv["lower"], lv["upper"], x[idx], mode=0)
         np.testing.assert_array_equal(_np(buf.flags)[idx], fl, err_msg=f"level {level}")
+        auto = _np(buf.flags).copy()
+        for form in (R.RSR_POPCOUNT, R.RSR_PERSIST):
+            other = R.rsr_classify(rsr_ctx, refs, buf.samples, N, R.RSR_LABEL, form)
+            np.testing.assert_array_equal(_np(other), auto, err_msg=f"level {level}, form {form}")
         Y, _ = oracle.eval_unknown(g, x, None, which=1, level=level)
         np.testing.assert_array_equal(_np(buf.Y), Y, err_msg=f"level {level}")
         assert est["P"] == float(Y.sum(dtype=np.int64)) / N
