@@ -23,6 +23,9 @@ namespace rsr {
 namespace {
 
 constexpr int kBlock = 256;
+// 16-flag chunks per thread of k_counts_vec: more blocks spread the pass over
+// more CUs, fewer blocks take fewer same-address ticket atomics.
+constexpr int kCountsChunks = 4;
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
@@ -113,12 +116,14 @@ __device__ __forceinline__ void count_word(uint32_t w, uint32_t y, uint32_t (&c)
 // The counts of k_counts for one job in one launch: 16 flags (and Y bytes)
 // per 16-byte load (both arrays 16-byte aligned), per-block partials, and the
 // last block to finish (a ticket counter, left at zero again) adds them into
-// out[0..4].
+// out[0..4] and copies *carry (0 when carry is NULL) into out[5].  out may be
+// pinned host memory.
 __global__ __launch_bounds__(kBlock) void k_counts_vec(const uint8_t* __restrict__ flags,
                                                        const uint8_t* __restrict__ Y, int64_t N,
                                                        unsigned long long* __restrict__ partial,
                                                        unsigned long long* __restrict__ out,
-                                                       unsigned int* __restrict__ ticket) {
+                                                       unsigned int* __restrict__ ticket,
+                                                       const unsigned long long* __restrict__ carry) {
     uint32_t c[5] = {0, 0, 0, 0, 0};
     const int64_t chunks = N >> 4;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
@@ -181,7 +186,10 @@ __global__ __launch_bounds__(kBlock) void k_counts_vec(const uint8_t* __restrict
         for (int w = 0; w < kBlock / 64; ++w) sum += red64[w][threadIdx.x];
         out[threadIdx.x] = sum;
     }
+    if (threadIdx.x == 5) out[5] = carry ? *carry : 0ull;
     if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Host memory: the stores reach it before the kernel is seen to end.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 }
 
 // Sums the per-block partials of k_counts into out[0..4] (one block per job).
@@ -490,14 +498,15 @@ hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* 
 }
 
 hipError_t launch_counts_vec(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
-                             uint64_t* d_counters, uint64_t* d_partial, uint32_t* d_ticket) {
-    // Four 16-flag chunks per thread: fewer blocks contend for the ticket.
-    int64_t blocks = ((N >> 4) + kBlock * 4 - 1) / (kBlock * 4);
+                             uint64_t* out, uint64_t* d_partial, uint32_t* d_ticket,
+                             const uint64_t* d_carry) {
+    int64_t blocks = ((N >> 4) + kBlock * kCountsChunks - 1) / (kBlock * kCountsChunks);
     if (blocks > kMaxReduceBlocks) blocks = kMaxReduceBlocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_counts_vec, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
                        d_flags, d_Y, N, reinterpret_cast<unsigned long long*>(d_partial),
-                       reinterpret_cast<unsigned long long*>(d_counters), d_ticket);
+                       reinterpret_cast<unsigned long long*>(out), d_ticket,
+                       reinterpret_cast<const unsigned long long*>(d_carry));
     return hipGetLastError();
 }
 

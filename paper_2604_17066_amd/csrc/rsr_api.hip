@@ -318,6 +318,9 @@ rsr_status rsr_ctx_create(int device, void* hip_stream, rsr_ctx** out) {
                                                 rsr::kMaxGradBlocks) != hipSuccess ||
         rsr::host_malloc(&ctx->ws.host_counts, sizeof(uint64_t) * 16) != hipSuccess)
         st = RSR_ENOMEM;
+    if (st == RSR_OK && hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->ws.host_counts_dev),
+                                                ctx->ws.host_counts, 0) != hipSuccess)
+        st = RSR_EHIP;
     if (st == RSR_OK && rsr::noalloc_scratch(device, &ctx->noalloc_scratch) != hipSuccess)
         st = RSR_EHIP;
     // counters[15] is the ticket of the one-launch counts kernel, which
@@ -887,18 +890,25 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
     DeviceGuard g(ctx->device);
     const bool aligned = (reinterpret_cast<uintptr_t>(d_flags) & 15u) == 0 &&
                          (reinterpret_cast<uintptr_t>(d_Y) & 15u) == 0;
-    if (aligned)
-        RSR_HIP(ctx, rsr::launch_counts_vec(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
+    // host_counts[0..4] receive the counts and host_counts[5] the persistent
+    // cascade's time-out flag (counters[14]); the one-launch kernel writes
+    // them into the pinned buffer itself, the other path through a copy.
+    uint64_t* c = ctx->ws.host_counts;
+    if (aligned) {
+        RSR_HIP(ctx, rsr::launch_counts_vec(ctx->stream, d_flags, d_Y, N, ctx->ws.host_counts_dev,
                                             ctx->ws.count_part,
-                                            reinterpret_cast<uint32_t*>(ctx->ws.counters + 15)));
-    else
+                                            reinterpret_cast<uint32_t*>(ctx->ws.counters + 15),
+                                            ctx->ws.counters + 14));
+        RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    } else {
         RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
                                         ctx->ws.count_part));
-    RSR_HIP(ctx, hipMemcpyAsync(ctx->ws.host_counts, ctx->ws.counters, sizeof(uint64_t) * 16,
-                                hipMemcpyDeviceToHost, ctx->stream));
-    RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const uint64_t* c = ctx->ws.host_counts;
-    if (c[14] != 0) {
+        RSR_HIP(ctx, hipMemcpyAsync(c, ctx->ws.counters, sizeof(uint64_t) * 16,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        c[5] = c[14];
+    }
+    if (c[5] != 0) {
         // A persistent cascade since the last check could not synchronise its
         // blocks in time: its flags are not to be trusted.
         RSR_HIP(ctx, rsr::launch_fill_u64(ctx->stream, ctx->ws.counters + 14, 1, 0));
