@@ -498,10 +498,14 @@ def test_grad_counts_any_run_length(rsr_ctx, n, K, N):
 
 
 @pytest.mark.parametrize("N,offset,with_Y", [(1_000_003, 0, True), (1_000_003, 1, True),
-                                             (15, 0, True), (16, 0, False), (70_001, 3, False)])
+                                             (15, 0, True), (16, 0, False), (70_001, 3, False),
+                                             (1_000_000, 0, False), (1 << 24, 0, True),
+                                             ((1 << 24) + 37, 0, True)])
 def test_estimate_counts_any_alignment(rsr_ctx, N, offset, with_Y):
     """Counts of rsr_estimate: 16-byte aligned flags and Y take the one-launch
-    kernel (16 flags per load, a ragged tail of up to 15), others the
+    kernel (16 flags per load, a ragged tail of up to 15; a grid of at most
+    1024 blocks, so from 2^24 flags on a thread takes more than four loads),
+    others the
     per-byte kernels; flags hold every value 0..3 and Y is 0, 1 or larger
     (counted as 1).  Exact against the oracle, and repeated calls agree."""
     rng = np.random.default_rng(N + offset)
