@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
     for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBlock * S; b0 < total;
          b0 += static_cast<int64_t>(gridDim.x) * kBlock * S) {
         const int64_t j0 = b0 + static_cast<int64_t>(wave) * 64 * S;
-        uint32_t x[S][W], nx[S][W];
+        uint32_t x[S][W];
         bool valid[S];
         int64_t jj[S], gg[S];
 #pragma unroll
@@ -77,13 +77,12 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 x[s][w] = (valid[s] && w < w_real) ? base[w * stride + at] : 0u;
-                nx[s][w] = ~x[s][w];
             }
         }
         uint32_t mnL[S], mnU[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
-        test_rows<W, S, kBlock>(x, nx, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
+        test_rows<W, S, kBlock>(x, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
         bool carry[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -134,14 +133,13 @@ __global__ __launch_bounds__(kBlock) void k_casc_test(
         const int64_t d = b0 + threadIdx.x;
         bool live[1];
         live[0] = d < total && match[d] == 0u;
-        uint32_t x[1][W], nx[1][W];
+        uint32_t x[1][W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             x[0][w] = (live[0] && w < w_real) ? csrc[w * cstride + d] : 0u;
-            nx[0][w] = ~x[0][w];
         }
         uint32_t mnL[1] = {0xFFFFFFFFu}, mnU[1] = {0xFFFFFFFFu};
-        test_rows<W, 1, kBlock>(x, nx, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU, s_rows);
+        test_rows<W, 1, kBlock>(x, live, low_n, cl0, cl1, up_b, cu0, cu1, mnL, mnU, s_rows);
         const uint32_t bits = (mnL[0] == 0u ? 1u : 0u) | (mnU[0] == 0u ? 2u : 0u);
         if (live[0] && bits) atomicOr(&match[d], bits);
     }

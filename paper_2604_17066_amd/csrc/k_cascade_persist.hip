@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_r0(SegSrc seg, int w_real,
     // Block-uniform loop (test_rows synchronises the block).
     for (int64_t b0 = begin; b0 < end; b0 += static_cast<int64_t>(kBlock) * S) {
         const int64_t j0 = b0 + static_cast<int64_t>(wave) * 64 * S;
-        uint32_t x[S][W], nx[S][W];
+        uint32_t x[S][W];
         bool valid[S];
         int64_t gg[S];
 #pragma unroll
@@ -147,13 +147,12 @@ __global__ __launch_bounds__(kBlock) void k_casc_r0(SegSrc seg, int w_real,
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 x[s][w] = (valid[s] && w < w_real) ? base[w * stride + at] : 0u;
-                nx[s][w] = ~x[s][w];
             }
         }
         uint32_t mnL[S], mnU[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
-        test_rows<W, S, kBlock>(x, nx, valid, low_n, 0, l1, up_b, 0, u1, mnL, mnU, s_rows);
+        test_rows<W, S, kBlock>(x, valid, low_n, 0, l1, up_b, 0, u1, mnL, mnU, s_rows);
         bool carry[S];
         uint64_t mask[S];
 #pragma unroll
