@@ -37,8 +37,8 @@ MFMA_FP4_PEAK_FLOPS = 10.1e15
 # changes, until the counters are taken again.
 COUNT_TRAFFIC_BYTES = {
     "popcount": (50.42 + 0.95) * 2 ** 20,
-    "mfma": (433.88 + 0.95) * 2 ** 20,
-    "mfma_fp4": (63.40 + 0.95) * 2 ** 20,
+    "mfma": (434.04 + 0.95) * 2 ** 20,
+    "mfma_fp4": (63.48 + 0.95) * 2 ** 20,
 }
 
 
