@@ -41,23 +41,28 @@ using namespace casc;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxChunks = 64;
+// Round 0 (every sample) in blocks of 512: half the slot reservations of
+// 256-thread blocks on the one output counter (graph2: 0.150 against 0.153 ms
+// per LABEL classify; the later rounds keep 256, where 512 is slower).
+constexpr int kRound0Block = 512;
 
-template <int W, int S>
-__global__ __launch_bounds__(kBlock) void k_casc_fused(
+template <int W, int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_casc_fused(
     SegSrc seg, const uint32_t* __restrict__ csrc, int64_t cstride,
     const int32_t* __restrict__ src_idx, const unsigned long long* __restrict__ src_count,
     int w_real, const uint32_t* __restrict__ low_n, int l0, int l1,
     const uint32_t* __restrict__ up_b, int u0, int u1, uint32_t* __restrict__ dst,
     int32_t* __restrict__ dst_idx, uint32_t* __restrict__ dst_match, int64_t dst_stride,
     unsigned long long* __restrict__ dst_count, int last) {
-    __shared__ int s_counts[S * kWaves];
+    constexpr int kW = BLOCK / 64;
+    __shared__ int s_counts[S * kW];
     __shared__ unsigned long long s_base;
     __shared__ uint32_t s_rows[2 * tile_rows<W>() * W];
     const int64_t total = src_idx ? static_cast<int64_t>(*src_count) : seg.total;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // Block-uniform loop (test_rows and block_reserve synchronise the block).
-    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBlock * S; b0 < total;
-         b0 += static_cast<int64_t>(gridDim.x) * kBlock * S) {
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * BLOCK * S; b0 < total;
+         b0 += static_cast<int64_t>(gridDim.x) * BLOCK * S) {
         const int64_t j0 = b0 + static_cast<int64_t>(wave) * 64 * S;
         uint32_t x[S][W];
         bool valid[S];
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
         uint32_t mnL[S], mnU[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) mnL[s] = mnU[s] = 0xFFFFFFFFu;
-        test_rows<W, S, kBlock>(x, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
+        test_rows<W, S, BLOCK>(x, valid, low_n, l0, l1, up_b, u0, u1, mnL, mnU, s_rows);
         bool carry[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_casc_fused(
         }
         if (last) continue;
         int64_t d[S];
-        block_reserve<kWaves, S>(carry, dst_count, s_counts, &s_base, d);
+        block_reserve<kW, S>(carry, dst_count, s_counts, &s_base, d);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (carry[s]) {
@@ -226,13 +231,13 @@ hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
                                        cb.stride, dst_count, last ? 1 : 0);
         } else if (chunks == 1) {
             if (round == 0)
-                hipLaunchKernelGGL((k_casc_fused<W, S0>), dim3(static_cast<unsigned>(
-                                       blocks_for(static_cast<int64_t>(kBlock) * S0, grid_cap))),
-                                   dim3(kBlock), 0, st, seg, csrc, cb.stride, src_idx, src_count,
+                hipLaunchKernelGGL((k_casc_fused<W, S0, kRound0Block>), dim3(static_cast<unsigned>(
+                                       blocks_for(static_cast<int64_t>(kRound0Block) * S0, grid_cap))),
+                                   dim3(kRound0Block), 0, st, seg, csrc, cb.stride, src_idx, src_count,
                                    refs->W, refs->d_lower_nbits, l0, l1, refs->d_upper_bits, u0,
                                    u1, dst, dst_idx, dst_match, cb.stride, dst_count, last ? 1 : 0);
             else
-                hipLaunchKernelGGL((k_casc_fused<W, 1>), dim3(static_cast<unsigned>(
+                hipLaunchKernelGGL((k_casc_fused<W, 1, kBlock>), dim3(static_cast<unsigned>(
                                        blocks_for(kBlock, grid_cap))),
                                    dim3(kBlock), 0, st, seg, csrc, cb.stride, src_idx, src_count,
                                    refs->W, refs->d_lower_nbits, l0, l1, refs->d_upper_bits, u0,
