@@ -33,12 +33,15 @@ constexpr int tile_rows() {
 // coalesced cooperative load per tile; the reads are wave-uniform, so every
 // LDS access is a broadcast).  A wave stops testing once all its live lanes
 // have matched (vote every 8 rows); the block leaves when every wave has.
-// Every thread of the block must call it.
+// Lower rows are stored as NOT t(r), so x <= r iff the OR over the words of
+// x & row is 0; upper rows as t(r), so x >= r iff the OR of ~x & row is 0.
+// mnL / mnU keep the minimum of those ORs (0: some row matched).  Every
+// thread of the block must call it.
 template <int W, int S, int BLOCK>
-__device__ __forceinline__ void test_rows(const uint32_t (&x)[S][W], const bool (&live)[S], const uint32_t* __restrict__ low_n,
-                                          int l0, int l1, const uint32_t* __restrict__ up_b,
-                                          int u0, int u1, uint32_t (&mnL)[S],
-                                          uint32_t (&mnU)[S], uint32_t* lds) {
+__device__ __forceinline__ void test_rows(const uint32_t (&x)[S][W], const bool (&live)[S],
+                                          const uint32_t* __restrict__ low_n, int l0, int l1,
+                                          const uint32_t* __restrict__ up_b, int u0, int u1,
+                                          uint32_t (&mnL)[S], uint32_t (&mnU)[S], uint32_t* lds) {
     constexpr int T = tile_rows<W>();
     const int nL = l1 - l0, nU = u1 - u0;
     const int n_max = nL > nU ? nL : nU;
