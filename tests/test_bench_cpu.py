@@ -21,3 +21,22 @@ def test_bench_help_lists_the_contract_flags():
     assert r.returncode == 0
     for flag in ("--gpus", "--steps", "--warmup"):
         assert flag in r.stdout
+
+
+def test_cpu_baseline_budget_fit():
+    """The CPU baselines' sample sizing grows the sample until one run takes a
+    quarter of the budget or reaches the cap, and returns that last run."""
+    sys.path.insert(0, ROOT)
+    import bench
+    calls = []
+
+    def run(n):
+        calls.append(n)
+        return n * 1e-3 + 0.01, n        # a fixed cost plus a per-sample cost
+
+    n, t, res = bench._fit_to_budget(run, 4.0, 16, 10**9)
+    assert t >= 1.0 and res == n and calls[-1] == n and calls == sorted(calls)
+    n, t, res = bench._fit_to_budget(run, 4.0, 16, 100)      # the cap ends it first
+    assert n == 100 and t < 1.0
+    n, t, res = bench._fit_to_budget(run, 4.0, 5000, 10**9)  # the first run is enough
+    assert n == 5000 and len([c for c in calls if c == 5000]) == 1
