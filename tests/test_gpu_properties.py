@@ -94,3 +94,56 @@ def test_random_systems_every_form(rsr_ctx, sysd, keep_l, keep_u, N):
     for form in (R.RSR_POPCOUNT, R.RSR_MFMA, R.RSR_MFMA_FP4, R.RSR_AUTO, R.RSR_PERSIST):
         fl = R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, form)
         np.testing.assert_array_equal(_np(fl), ol, err_msg=f"LABEL flags, form {form}")
+
+
+@st.composite
+def st_plans(draw):
+    """One to three random systems (each with its own K and level), one to
+    three jobs per system with their own probabilities, seeds and sample
+    counts (1 to 4000), and random subsets of the reference rows."""
+    systems = []
+    for _ in range(draw(st.integers(1, 3))):
+        sysd = draw(st_systems(max_states=1 << 12))
+        keep = (draw(st.floats(0.0, 1.0)), draw(st.floats(0.0, 1.0)))
+        jobs = [(draw(st.integers(0, 2**31 - 1)), draw(st.integers(1, 4000)))
+                for _ in range(draw(st.integers(1, 3)))]
+        systems.append((sysd, keep, jobs))
+    return systems
+
+
+@settings(max_examples=20, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.filter_too_much])
+@given(st_plans())
+def test_random_plans_equal_the_plain_path(rsr_ctx, plan_d):
+    """A plan over random systems and jobs (segments of different widths, K
+    and levels in one captured graph): every job's flags, Y and estimate
+    equal the plain one-job path's, and its flags the oracle's."""
+    jobs, plain = [], []
+    for (graph, K, level, p0, seed), (keep_l, keep_u), job_list in plan_d:
+        n = graph["edge_u"].size
+        lo, up = _refs(graph, K, level, seed, keep_l, keep_u)
+        refs = R.Refs(rsr_ctx, n, K, lo, up)
+        sysm = R.System(rsr_ctx, graph, K=K, level=level)
+        for jseed, N in job_list:
+            rng = np.random.default_rng(jseed)
+            p = rng.uniform(0.05, 1.0, (n, K))
+            p /= p.sum(axis=1, keepdims=True)
+            m = R.Model(rsr_ctx, np.ascontiguousarray(p))
+            jobs.append({"model": m, "refs": refs, "system": sysm, "seed": jseed, "N": N,
+                         "buffers": R.Buffers(rsr_ctx, n, K, N), "grad": True})
+            plain.append((lo, up, p, graph, level))
+    print(f"plan: {len(plan_d)} systems, {len(jobs)} jobs, N = {[jb['N'] for jb in jobs]}", flush=True)
+    plan = R.Plan(rsr_ctx, jobs, tune=False)
+    plan.run()
+    est, _ = plan.results()
+    for k, (jb, (lo, up, p, graph, level)) in enumerate(zip(jobs, plain)):
+        N = jb["N"]
+        pe, pb = R.stage2(rsr_ctx, jb["model"], jb["refs"], jb["system"], N, jb["seed"])
+        b = jb["buffers"]
+        np.testing.assert_array_equal(_np(b.flags), _np(pb.flags), err_msg=f"job {k}")
+        np.testing.assert_array_equal(_np(b.Y), _np(pb.Y), err_msg=f"job {k}")
+        assert est[k]["P"] == pe["P"] and est[k]["n_u"] == pe["n_u"], k
+        x = oracle.sample(p, jb["seed"], 0, 0, N)
+        fl, _, _ = oracle.classify(lo, up, x, mode=0)
+        np.testing.assert_array_equal(_np(b.flags), fl, err_msg=f"job {k} against the oracle")
+    plan.close()
