@@ -147,3 +147,45 @@ def test_random_plans_equal_the_plain_path(rsr_ctx, plan_d):
         fl, _, _ = oracle.classify(lo, up, x, mode=0)
         np.testing.assert_array_equal(_np(b.flags), fl, err_msg=f"job {k} against the oracle")
     plan.close()
+
+
+@SETTINGS
+@given(st_systems(max_states=1 << 12), st.sampled_from(("global", "flow")), st.integers(1, 3),
+       st.floats(0.0, 1.0), st.floats(0.0, 1.0), st.integers(1, 3000))
+def test_random_global_and_flow_systems(rsr_ctx, sysd, kind, d, keep_l, keep_u, N):
+    """The other system kinds on random multigraphs: global connectivity
+    (K = 2, level 1 or 2) and maximum s-t flow >= d (capacities 0..K-1, d =
+    1..3), reference rows from the brute-force state tables; the Stage-2
+    path's flags, Y and counts equal the oracle's."""
+    graph, K, _, p, seed = sysd
+    n = graph["edge_u"].size
+    rng = np.random.default_rng(seed + 3)
+    if kind == "global":
+        K, level = 2, 1 + (d - 1) % 2
+        p = rng.uniform(0.05, 1.0, (n, 2))
+        p = np.ascontiguousarray(p / p.sum(axis=1, keepdims=True))
+        table = oracle.state_table_global(graph, 2)
+        sysm = R.System(rsr_ctx, graph, level=level, kind="global")
+    else:
+        level = d
+        table = oracle.maxflow_table(graph, K)
+        sysm = R.System(rsr_ctx, graph, K=K, level=level, kind="flow")
+    lo, up = oracle.reference_sets(table, n, K, level=level)
+    lo = np.ascontiguousarray(lo[rng.random(len(lo)) < keep_l])
+    up = np.ascontiguousarray(up[rng.random(len(up)) < keep_u])
+    print(f"{kind} K={K} level={level} n={n} rows={len(lo)}+{len(up)} N={N} seed={seed}", flush=True)
+    m = R.Model(rsr_ctx, p)
+    refs = R.Refs(rsr_ctx, n, K, lo, up)
+    est, buf = R.stage2(rsr_ctx, m, refs, sysm, N, seed)
+    x = oracle.sample(p, seed, 0, 0, N)
+    fl, _, _ = oracle.classify(lo, up, x, mode=0)
+    if kind == "global":
+        Y, nev = oracle.eval_unknown_global(graph, x, fl, which=0, level=level)
+    else:
+        Y, nev = oracle.eval_unknown_flow(graph, x, fl, which=0, demand=level)
+    np.testing.assert_array_equal(_np(buf.flags), fl)
+    np.testing.assert_array_equal(_np(buf.Y), Y)
+    assert int(_np(buf.n_eval)[0]) == nev
+    cnt = oracle.counts(fl, Y)
+    for k, name in enumerate(oracle.COUNT_NAMES):
+        assert est[name] == int(cnt[k]), name
