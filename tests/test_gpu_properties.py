@@ -189,3 +189,41 @@ def test_random_global_and_flow_systems(rsr_ctx, sysd, kind, d, keep_l, keep_u, 
     cnt = oracle.counts(fl, Y)
     for k, name in enumerate(oracle.COUNT_NAMES):
         assert est[name] == int(cnt[k]), name
+
+
+@SETTINGS
+@given(st_systems(max_states=1 << 12), st.sampled_from(("st", "global", "flow")), st.integers(1, 3),
+       st.integers(1, 2000), st.integers(1, 256))
+def test_random_boundary_searches(rsr_ctx, sysd, kind, d, N, n_pick):
+    """The componentwise boundary search (section 3.4) on random multigraphs
+    of every system kind, from random picks (repeats allowed): rows and sides
+    equal the oracle's search, which evaluates the system function at every
+    single step."""
+    graph, K, level, p, seed = sysd
+    n = graph["edge_u"].size
+    rng = np.random.default_rng(seed + 5)
+    if kind == "global":
+        K, level = 2, 1 + (d - 1) % 2
+        p = rng.uniform(0.05, 1.0, (n, 2))
+        p = np.ascontiguousarray(p / p.sum(axis=1, keepdims=True))
+        sysm = R.System(rsr_ctx, graph, level=level, kind="global")
+    elif kind == "flow":
+        level = d
+        sysm = R.System(rsr_ctx, graph, K=K, level=level, kind="flow")
+    else:
+        sysm = R.System(rsr_ctx, graph, K=K, level=level)
+    picks = rng.integers(0, N, n_pick).astype(np.int64)
+    print(f"{kind} K={K} level={level} n={n} N={N} picks={n_pick} seed={seed}", flush=True)
+    m = R.Model(rsr_ctx, p)
+    xs = R.rsr_sample(rsr_ctx, m, seed, 0, 0, N)
+    rows, side = R.rsr_boundary_search(rsr_ctx, sysm, xs, N,
+                                       torch.tensor(picks, dtype=torch.int64, device=rsr_ctx.device))
+    x = oracle.sample(p, seed, 0, 0, N)[picks]
+    if kind == "global":
+        want_rows, want_side, _ = oracle.boundary_global(graph, x, K=2, level=level)
+    elif kind == "flow":
+        want_rows, want_side, _ = oracle.boundary_flow(graph, x, K, level)
+    else:
+        want_rows, want_side, _ = oracle.boundary_st(graph, x, K=K, level=level)
+    np.testing.assert_array_equal(_np(side), want_side)
+    np.testing.assert_array_equal(_np(rows), want_rows)
