@@ -227,3 +227,37 @@ def test_random_boundary_searches(rsr_ctx, sysd, kind, d, N, n_pick):
         want_rows, want_side, _ = oracle.boundary_st(graph, x, K=K, level=level)
     np.testing.assert_array_equal(_np(side), want_side)
     np.testing.assert_array_equal(_np(rows), want_rows)
+
+
+@settings(max_examples=25, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.filter_too_much])
+@given(st_systems(max_states=1 << 12), st.sampled_from(("st", "global", "flow")), st.integers(1, 3),
+       st.integers(64, 3000), st.integers(1, 48), st.integers(2, 400), st.integers(1, 12))
+def test_random_stage1_loops(rsr_ctx, sysd, kind, d, N, picks, max_rows, iters):
+    """The Stage-1 loop (section 3.5) on random multigraphs of every system
+    kind, from empty reference sets: the same rows in the same order, the same
+    iteration count, unclassified fraction, searches and duplicates as the
+    oracle's loop."""
+    graph, K, level, p, seed = sysd
+    n = graph["edge_u"].size
+    rng = np.random.default_rng(seed + 7)
+    if kind == "global":
+        K, level = 2, 1 + (d - 1) % 2
+        p = rng.uniform(0.05, 1.0, (n, 2))
+        p = np.ascontiguousarray(p / p.sum(axis=1, keepdims=True))
+        sysm = R.System(rsr_ctx, graph, level=level, kind="global")
+    elif kind == "flow":
+        level = d
+        sysm = R.System(rsr_ctx, graph, K=K, level=level, kind="flow")
+    else:
+        sysm = R.System(rsr_ctx, graph, K=K, level=level)
+    print(f"{kind} K={K} level={level} n={n} N={N} picks={picks} rows<={max_rows} iters={iters}",
+          flush=True)
+    m = R.Model(rsr_ctx, p)
+    lo, up, info = R.stage1(rsr_ctx, m, sysm, N, picks, 1e-9, max_rows, iters, seed)
+    wlo, wup, winfo = oracle.stage1(graph, p, N, picks, 1e-9, max_rows, iters, seed, K=K,
+                                    level=level, kind=kind)
+    for key in ("iterations", "p_u", "searches", "duplicates"):
+        assert info[key] == winfo[key], key
+    np.testing.assert_array_equal(lo, wlo)
+    np.testing.assert_array_equal(up, wup)
