@@ -40,7 +40,12 @@ using namespace casc;
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+// Most chunks of a split round: 64 in the FP4 form (more slow the 1250-edge
+// graph's rounds of 3e4-6e4 rows: 2.47 against 2.19 ms per classify), 128 in
+// the popcount form (its rounds gain from the parallelism: three-state level
+// 1 0.36 against 0.44 ms).
 constexpr int kMaxChunks = 64;
+constexpr int kMaxPopcountChunks = 128;
 // Round 0 (every sample) in blocks of 512: half the slot reservations of
 // 256-thread blocks on the one output counter (graph2: 0.150 against 0.153 ms
 // per LABEL classify; the later rounds keep 256, where 512 is slower).
@@ -210,7 +215,8 @@ hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
         const int u1 = static_cast<int>(hi < refs->R_U ? hi : refs->R_U);
         const int rows = (l1 - l0) > (u1 - u0) ? (l1 - l0) : (u1 - u0);
         int chunks = round == 0 ? 1 : rows / (shape.split_rows > 0 ? shape.split_rows : 1 << 30);
-        if (chunks > kMaxChunks) chunks = kMaxChunks;
+        const int max_chunks = shape.mfma_tail && refs->KS4 > 0 ? kMaxChunks : kMaxPopcountChunks;
+        if (chunks > max_chunks) chunks = max_chunks;
         if (chunks < 1) chunks = 1;
         uint32_t* dst = cb.words[round & 1];
         int32_t* dst_idx = cb.index[round & 1];

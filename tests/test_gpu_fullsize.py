@@ -4,9 +4,13 @@
   level, N = 1e6): every Y of both levels equals the oracle's plain Monte
   Carlo, flags on sampled indices equal the oracle's Algorithm 1, P is
   bit-exact and the fp32 gradient is within 1e-5 of the fp64 oracle.  The
-  LABEL flags of the popcount cascade (whose round over rows 4 000..20 000
-  wants 125 chunks of 128 rows and is held to the cap of 64 chunks) and of
-  the persistent cascade equal the automatic form's on every sample.
+  LABEL flags of the popcount cascade and of the persistent cascade equal
+  the automatic form's on every sample.
+* The 1250-edge graph with 4.5e4 + 4.5e4 reference rows: the automatic
+  form's FP4 round over rows 8 192..45 000 wants 71 chunks of 512 rows and
+  is held to the cap of 64, the popcount form's round over rows
+  20 000..45 000 wants 195 chunks of 128 rows and is held to its cap of
+  128; both equal the persistent cascade and the oracle.
 * One job of the batched workload at its full reference-set size (the
   647-edge graph, 2.2e4 + 2.2e4 rows) inside a plan, against the oracle.
 """
@@ -65,6 +69,26 @@ def test_multistate_config_size(rsr_ctx):
         c, G64 = oracle.grad(cfg["p"], x, Y)
         np.testing.assert_array_equal(_np(counts).view(np.uint64), c)
         _grad_close(_np(G), G64)
+
+
+def test_wide_graph_chunk_caps(rsr_ctx):
+    cfg = WL.configs.batched(n_scen=1, N=1, graphs=[7], ref_scale=0.45)
+    sd, jd = cfg["systems"][0], cfg["jobs"][0]
+    n, N = sd["n"], 20_000
+    refs = R.Refs(rsr_ctx, n, 2, sd["lower"], sd["upper"])
+    # Both rounds exceed their caps: (R - 8192) / 512 > 64, (R - 20000) / 128 > 128.
+    assert refs.consistent and min(refs.R_L, refs.R_U) >= 42_000
+    m = R.Model(rsr_ctx, jd["p"])
+    xs = R.rsr_sample(rsr_ctx, m, jd["seed"], 0, 0, N)
+    flags = {f: _np(R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_LABEL, f)).copy()
+             for f in (R.RSR_AUTO, R.RSR_POPCOUNT, R.RSR_PERSIST)}
+    np.testing.assert_array_equal(flags[R.RSR_POPCOUNT], flags[R.RSR_AUTO])
+    np.testing.assert_array_equal(flags[R.RSR_PERSIST], flags[R.RSR_AUTO])
+    idx = np.unique(np.random.default_rng(71).integers(0, N, 400))
+    x = oracle.sample_at(jd["p"], jd["seed"], 0, idx.astype(np.uint64))
+    want, _, _ = oracle.classify(sd["lower"], sd["upper"], x, mode=0)
+    np.testing.assert_array_equal(flags[R.RSR_AUTO][idx], want)
+    print("unclassified", int((flags[R.RSR_AUTO] == 0).sum()), "of", N)
 
 
 def test_batched_job_full_reference_size(rsr_ctx):
