@@ -254,7 +254,12 @@ rsr_status rsr_eval_unknown(rsr_ctx* ctx, const rsr_system* sys, const uint32_t*
                             uint64_t* d_n_evaluated);
 
 /* Reduces flags (and Y, if not NULL) to counts on the device, copies them to
- * the host, synchronises the stream and fills *out as rsr_estimate_t says.
+ * the host and fills *out as rsr_estimate_t says.  It returns when the counts
+ * have reached the host: every earlier operation of the context's stream has
+ * then ended, and the counting kernel has read all of flags and Y (with
+ * 16-byte aligned flags and Y that kernel's last block publishes the counts
+ * and the host returns at once; its exit may still be in flight, ordered
+ * before any later work of the stream).
  * With d_Y == NULL, n_u_up = 0 and P, se, cov are NaN (bounds only).
  * EHIP: a device error, or a persistent cascade since the previous call
  * whose grid barrier timed out (the flag is cleared with the report). */

@@ -117,13 +117,16 @@ __device__ __forceinline__ void count_word(uint32_t w, uint32_t y, uint32_t (&c)
 // per 16-byte load (both arrays 16-byte aligned), per-block partials, and the
 // last block to finish (a ticket counter, left at zero again) adds them into
 // out[0..4] and copies *carry (0 when carry is NULL) into out[5].  out may be
-// pinned host memory.
+// pinned host memory.  When seq is not 0 the last block then stores seq into
+// out[6], ordered after out[0..5] at system scope, so that a host polling
+// out[6] may read the counts before the kernel is seen to end.
 __global__ __launch_bounds__(kBlock) void k_counts_vec(const uint8_t* __restrict__ flags,
                                                        const uint8_t* __restrict__ Y, int64_t N,
                                                        unsigned long long* __restrict__ partial,
                                                        unsigned long long* __restrict__ out,
                                                        unsigned int* __restrict__ ticket,
-                                                       const unsigned long long* __restrict__ carry) {
+                                                       const unsigned long long* __restrict__ carry,
+                                                       unsigned long long seq) {
     uint32_t c[5] = {0, 0, 0, 0, 0};
     const int64_t chunks = N >> 4;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
@@ -190,6 +193,11 @@ __global__ __launch_bounds__(kBlock) void k_counts_vec(const uint8_t* __restrict
     if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // Host memory: the stores reach it before the kernel is seen to end.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (seq == 0) return;
+    // Every writer of out[0..5] has passed its release before the barrier.
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&out[6], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Sums the per-block partials of k_counts into out[0..4] (one block per job).
@@ -499,14 +507,15 @@ hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* 
 
 hipError_t launch_counts_vec(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
                              uint64_t* out, uint64_t* d_partial, uint32_t* d_ticket,
-                             const uint64_t* d_carry) {
+                             const uint64_t* d_carry, uint64_t seq) {
     int64_t blocks = ((N >> 4) + kBlock * kCountsChunks - 1) / (kBlock * kCountsChunks);
     if (blocks > kMaxReduceBlocks) blocks = kMaxReduceBlocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_counts_vec, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
                        d_flags, d_Y, N, reinterpret_cast<unsigned long long*>(d_partial),
                        reinterpret_cast<unsigned long long*>(out), d_ticket,
-                       reinterpret_cast<const unsigned long long*>(d_carry));
+                       reinterpret_cast<const unsigned long long*>(d_carry),
+                       static_cast<unsigned long long>(seq));
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -895,11 +896,30 @@ rsr_status rsr_estimate(rsr_ctx* ctx, const uint8_t* d_flags, const uint8_t* d_Y
     // them into the pinned buffer itself, the other path through a copy.
     uint64_t* c = ctx->ws.host_counts;
     if (aligned) {
+        // The kernel's last block stores this call's sequence number into
+        // c[6] after the counts (system-scope release), once every earlier
+        // kernel of the stream and every other block of its own have ended:
+        // the host returns as soon as it sees it, instead of waiting for the
+        // end-of-kernel signal.  Past 10 ms of polling (a long queue ahead of
+        // the counts) it synchronises the stream.
+        const uint64_t seq = ++ctx->ws.estimate_seq;
+        __atomic_store_n(&c[6], uint64_t{0}, __ATOMIC_RELAXED);
         RSR_HIP(ctx, rsr::launch_counts_vec(ctx->stream, d_flags, d_Y, N, ctx->ws.host_counts_dev,
                                             ctx->ws.count_part,
                                             reinterpret_cast<uint32_t*>(ctx->ws.counters + 15),
-                                            ctx->ws.counters + 14));
-        RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                                            ctx->ws.counters + 14, seq));
+        const auto t0 = std::chrono::steady_clock::now();
+        bool seen = false;
+        for (uint32_t it = 1;; ++it) {
+            if (__atomic_load_n(&c[6], __ATOMIC_ACQUIRE) == seq) {
+                seen = true;
+                break;
+            }
+            if ((it & 255u) == 0 &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(10))
+                break;
+        }
+        if (!seen) RSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
     } else {
         RSR_HIP(ctx, rsr::launch_counts(ctx->stream, d_flags, d_Y, N, ctx->ws.counters,
                                         ctx->ws.count_part));

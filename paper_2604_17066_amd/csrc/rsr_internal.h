@@ -60,6 +60,7 @@ struct Workspace {
     uint32_t* grad_part = nullptr;     // [RSR_MAX_BITS * kMaxGradBlocks + kMaxGradBlocks] u32
     uint64_t* host_counts = nullptr;   // pinned, 16 u64
     uint64_t* host_counts_dev = nullptr;  // the device address of host_counts
+    uint64_t estimate_seq = 0;         // last sequence number of rsr_estimate's counts
     uint64_t* casc_counters = nullptr; // [16] per-round cascade counters
     uint32_t* casc_words = nullptr;    // 2 x [W][N] u32 (cascade)
     int32_t* casc_index = nullptr;     // 2 x [N] i32 indices, then 2 x [N] u32 match words
@@ -370,10 +371,11 @@ hipError_t launch_counts(hipStream_t st, const uint8_t* d_flags, const uint8_t* 
 // One job's counts in one launch (flags and Y 16-byte aligned); d_ticket is a
 // zero-initialised u32 the kernel leaves at zero.
 // out[0..4] = n_L, n_U, n_u, n_both, n_u_up and out[5] = *d_carry (0 when
-// d_carry is NULL); out may be pinned host memory (its device address).
+// d_carry is NULL); out may be pinned host memory (its device address).  A
+// nonzero seq is stored into out[6] after them (system-scope release).
 hipError_t launch_counts_vec(hipStream_t st, const uint8_t* d_flags, const uint8_t* d_Y, int64_t N,
                              uint64_t* out, uint64_t* d_partial, uint32_t* d_ticket,
-                             const uint64_t* d_carry);
+                             const uint64_t* d_carry, uint64_t seq);
 int64_t grad_blocks(int64_t N);
 hipError_t launch_grad(hipStream_t st, int n, int K, const float* d_p, const uint32_t* d_samples,
                        const uint8_t* d_Y, int64_t N, uint32_t* d_partial, float* d_G,

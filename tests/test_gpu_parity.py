@@ -523,6 +523,33 @@ def test_estimate_counts_any_alignment(rsr_ctx, N, offset, with_Y):
             assert est[name] == oest[k], name
 
 
+def test_estimate_after_long_queue(rsr_ctx):
+    """rsr_estimate returns once the counting kernel's last block has
+    published the call's sequence number next to the counts; with more than
+    10 ms of work queued before it (two exhaustive classifications of 2^20
+    samples against 5e4 + 5e4 rows) it synchronises the stream instead.  On
+    consecutive calls with different flags, either way, the counts are those
+    of the flags given, exact against the oracle."""
+    cfg = WL.configs.scaling(N=1 << 20, R_U=50_000, R_L=50_000)
+    N = cfg["N"]
+    _, xs = _sample(rsr_ctx, cfg["p"], cfg["seed"], 0, 0, N)
+    refs = R.Refs(rsr_ctx, cfg["n"], 2, cfg["lower"], cfg["upper"])
+    rng = np.random.default_rng(5)
+    flag_sets = [rng.integers(0, 4, N).astype(np.uint8) for _ in range(4)]
+    Y = rng.integers(0, 2, N).astype(np.uint8)
+    dev_Y = torch.from_numpy(Y).to(rsr_ctx.device)
+    dev = [torch.from_numpy(f).to(rsr_ctx.device) for f in flag_sets]
+    torch.cuda.synchronize()
+    for k, (f, d) in enumerate(zip(flag_sets, dev)):
+        if k % 2 == 0:
+            for _ in range(2):
+                R.rsr_classify(rsr_ctx, refs, xs, N, R.RSR_COUNT, R.RSR_POPCOUNT)
+        est = R.rsr_estimate(rsr_ctx, d, dev_Y, N)
+        want = oracle.counts(f, Y)
+        for j, name in enumerate(oracle.COUNT_NAMES):
+            assert est[name] == int(want[j]), (k, name)
+
+
 @pytest.mark.parametrize("g_idx,level", [(0, 1), (2, 1), (4, 1), (6, 1), (4, 2)])
 def test_eval_all_graph_sizes(rsr_ctx, g_idx, level):
     """s-t evaluation on graphs of 50 to 360 nodes (one to several node words
