@@ -406,7 +406,9 @@ typedef struct {
  *                     per job, 3 FP4 per job, 4 persistent cascade;
  *                     "first", "growth", "split": the cascade's round
  *                     rows; "tail": 0 popcount rounds, 1 FP4 rounds after
- *                     round 0, 2 FP4 rounds from round 0 on; "ms": the
+ *                     round 0, 2 FP4 rounds from round 0 on; "chunks"
+ *                     (optional on reading): most chunks of a split round,
+ *                     0 for the library's own caps; "ms": the
  *                     segment's classification time, timed on those
  *                     samples and scaled to all of them}.
  *                     Segments whose key is present take the stored choice

@@ -215,7 +215,9 @@ hipError_t cascade_w(hipStream_t st, const rsr_refs* refs, const SegSrc& seg,
         const int u1 = static_cast<int>(hi < refs->R_U ? hi : refs->R_U);
         const int rows = (l1 - l0) > (u1 - u0) ? (l1 - l0) : (u1 - u0);
         int chunks = round == 0 ? 1 : rows / (shape.split_rows > 0 ? shape.split_rows : 1 << 30);
-        const int max_chunks = shape.mfma_tail && refs->KS4 > 0 ? kMaxChunks : kMaxPopcountChunks;
+        const int max_chunks = shape.max_chunks > 0 ? shape.max_chunks
+                               : shape.mfma_tail && refs->KS4 > 0 ? kMaxChunks
+                                                                  : kMaxPopcountChunks;
         if (chunks > max_chunks) chunks = max_chunks;
         if (chunks < 1) chunks = 1;
         uint32_t* dst = cb.words[round & 1];

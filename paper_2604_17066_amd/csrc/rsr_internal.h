@@ -242,6 +242,8 @@ struct CascadeShape {
     // Round 0 in the FP4 32 x 32 form (k_casc_head) when first == 32 and
     // casc_head_supported(refs); otherwise on the vector ALU.
     bool mfma_head = false;
+    // Most chunks of a split round (1..1024); 0 takes the built-in caps.
+    int max_chunks = 0;
 };
 
 // Default shape with the matrix-core tail (measured on graph2: matrix-core

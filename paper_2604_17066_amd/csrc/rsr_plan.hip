@@ -50,15 +50,16 @@ struct Segment {
 
 // One entry of the tuning cache: the configuration chosen for a segment shape.
 struct TuneEntry {
-    int choice = 0, first = 0, growth = 0, split = 0, tail = 0;
+    int choice = 0, first = 0, growth = 0, split = 0, tail = 0, chunks = 0;
     double ms = 0.0;
 };
 
 // The tuning cache file is one JSON object: keys are segment-shape strings,
 // values are objects of numbers {"choice", "first", "growth", "split", "tail",
 // "ms"} ("tail": 0 popcount rounds, 1 matrix-core rounds after round 0, 2
-// matrix-core rounds from round 0 on).  This reader accepts exactly that (strings without escapes) and
-// returns false on anything else.
+// matrix-core rounds from round 0 on) and optionally "chunks" (most chunks of
+// a split round, 0 for the built-in caps).  This reader accepts exactly that
+// (strings without escapes) and returns false on anything else.
 class CacheReader {
   public:
     explicit CacheReader(const std::string& t) : t_(t) {}
@@ -143,13 +144,15 @@ class CacheReader {
             else if (k == "split") e.split = static_cast<int>(v), seen |= 8;
             else if (k == "tail") e.tail = static_cast<int>(v), seen |= 16;
             else if (k == "ms") e.ms = v, seen |= 32;
+            else if (k == "chunks") e.chunks = static_cast<int>(v), seen |= 64;
             else return false;
             ws();
             if (eat(',')) continue;
             if (eat('}')) break;
             return false;
         }
-        return seen == 63 && e.choice >= kCascade && e.choice <= kPersist &&
+        return (seen & 63) == 63 && e.choice >= kCascade && e.choice <= kPersist &&
+               e.chunks >= 0 && e.chunks <= 1024 &&
                (e.choice != kCascade || (e.first >= 1 && e.growth >= 2 && e.split >= 1));
     }
 };
@@ -332,8 +335,8 @@ rsr_status write_cache(rsr_ctx* ctx, const std::string& path,
         const TuneEntry& e = kv.second;
         std::fprintf(f,
                      "  \"%s\": {\"choice\": %d, \"first\": %d, \"growth\": %d, \"split\": %d, "
-                     "\"tail\": %d, \"ms\": %.6g}%s\n",
-                     kv.first.c_str(), e.choice, e.first, e.growth, e.split, e.tail, e.ms,
+                     "\"tail\": %d, \"chunks\": %d, \"ms\": %.6g}%s\n",
+                     kv.first.c_str(), e.choice, e.first, e.growth, e.split, e.tail, e.chunks, e.ms,
                      ++k < cache.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
@@ -422,6 +425,18 @@ rsr_status tune_segment(rsr_plan* p, int si) {
                 for (int sp : splits)
                     shapes.push_back({kCascade, rsr::CascadeShape{f, g, sp, tail, head}});
         if (st == RSR_OK) st = trial(shapes);
+        // Then the chosen shape with fewer and with more chunks per split
+        // round (the best cap depends on the rows and the survivors: 32 is
+        // the faster on 1e5 rows of 1250 bits, 64 on 4.7e4 rows of 900).
+        if (st == RSR_OK) {
+            std::vector<Cand> caps;
+            for (int mc : {32, 128}) {
+                rsr::CascadeShape c = s.shape;
+                c.max_chunks = mc;
+                caps.push_back({kCascade, c});
+            }
+            st = trial(caps);
+        }
     } else {
         std::vector<Cand> forms = {{kBitsPerJob, rsr::CascadeShape{}}};
         if (s.refs->KS > 0) forms.push_back({kMfmaPerJob, rsr::CascadeShape{}});
@@ -640,7 +655,8 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             if (it != cache.end()) {
                 const TuneEntry& te = it->second;
                 sg.choice = static_cast<Choice>(te.choice);
-                sg.shape = rsr::CascadeShape{te.first, te.growth, te.split, te.tail != 0, te.tail == 2};
+                sg.shape = rsr::CascadeShape{te.first, te.growth, te.split, te.tail != 0, te.tail == 2,
+                                             te.chunks};
                 sg.tuned_ms = static_cast<float>(te.ms);
                 // A stored choice the handle cannot run (no matrix-core
                 // operands, or a cascade on inconsistent rows) is retimed.
@@ -656,6 +672,7 @@ rsr_status rsr_plan_create(rsr_ctx* ctx, const rsr_job* jobs, int32_t n_jobs,
             te.first = sg.shape.first;
             te.growth = sg.shape.growth;
             te.split = sg.shape.split_rows;
+            te.chunks = sg.shape.max_chunks;
             te.tail = sg.shape.mfma_head ? 2 : (sg.shape.mfma_tail ? 1 : 0);
             te.ms = sg.tuned_ms;
             cache[key] = te;

@@ -149,7 +149,8 @@ def test_plan_tuning_cache(rsr_ctx, tmp_path):
     assert len(entries) == len(systems)
     for key, e in entries.items():
         assert key.startswith(torch.cuda.get_device_properties(0).gcnArchName)
-        assert set(e) == {"choice", "first", "growth", "split", "tail", "ms"}
+        assert set(e) == {"choice", "first", "growth", "split", "tail", "chunks", "ms"}
+        assert e["chunks"] in (0, 32, 128)
     plan.run()
     est1, g1 = plan.results()
     flags1 = [_np(jb["buffers"].flags).copy() for jb in jobs]
@@ -177,14 +178,17 @@ def test_plan_tuning_cache(rsr_ctx, tmp_path):
     assert bad.read_text() == '{"x": {"choice": 0}}'
 
 
-@pytest.mark.parametrize("choice,tail,first,growth,split", [(0, 0, 16, 4, 64), (0, 1, 16, 6, 256),
-                                                            (0, 1, 16, 8, 512), (0, 2, 32, 4, 64),
-                                                            (0, 2, 32, 8, 256), (4, 2, 32, 6, 256)])
-def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, growth, split):
+@pytest.mark.parametrize("choice,tail,first,growth,split,chunks",
+                         [(0, 0, 16, 4, 64, 0), (0, 1, 16, 6, 256, 0), (0, 1, 16, 8, 512, 0),
+                          (0, 2, 32, 4, 64, 0), (0, 2, 32, 8, 256, 0), (4, 2, 32, 6, 256, 0),
+                          (0, 0, 8, 4, 16, 2), (0, 1, 8, 4, 16, 1), (0, 1, 16, 4, 32, None)])
+def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, growth, split, chunks):
     """Every cascade a tuning cache can name (popcount rounds, matrix-core
     rounds after round 0, matrix-core rounds from round 0 on, the persistent
-    cascade: choice 4) gives the plain path's flags, Y and estimates on uneven
-    jobs sharing a launch, on two runs of the plan."""
+    cascade: choice 4; split rounds held to 1 or 2 chunks, or an entry
+    without "chunks", as written before the key existed) gives the plain
+    path's flags, Y and estimates on uneven jobs sharing a launch, on two
+    runs of the plan."""
     import json
     path = tmp_path / "tune.json"
     jobs, systems = _small_batch(rsr_ctx, n_scen=2, graphs=(1, 3), Ns=(20_000, 3_001, 777))
@@ -192,6 +196,10 @@ def test_plan_cached_cascade_shapes(rsr_ctx, tmp_path, choice, tail, first, grow
     entries = json.loads(path.read_text())
     for e in entries.values():
         e.update(choice=choice, first=first, growth=growth, split=split, tail=tail)
+        if chunks is None:
+            del e["chunks"]
+        else:
+            e["chunks"] = chunks
     path.write_text(json.dumps(entries))
     plan = R.Plan(rsr_ctx, jobs, tune=str(path))
     for rep in range(2):
