@@ -694,7 +694,8 @@ def batched_leg(ctx, ref_scale, reps, Ns=(1 << 18, 1_000_000), cpu_seconds=None)
                  4: "persistent cascade"}
         choices = sorted(({"key": k.split("/", 2)[2], "choice": names.get(v["choice"], "?"),
                            "tail": v["tail"], "first": v["first"], "growth": v["growth"],
-                           "split": v["split"], "classify_ms": v["ms"]} for k, v in entries.items()),
+                           "split": v["split"], "chunks": v.get("chunks", 0),
+                           "classify_ms": v["ms"]} for k, v in entries.items()),
                          key=lambda e: e["key"])
         same = all(a["P"] == b["P"] and a["n_u"] == b["n_u"] for a, b in zip(est, plain_est))
         plan.close()
