@@ -426,11 +426,12 @@ rsr_status tune_segment(rsr_plan* p, int si) {
                     shapes.push_back({kCascade, rsr::CascadeShape{f, g, sp, tail, head}});
         if (st == RSR_OK) st = trial(shapes);
         // Then the chosen shape with fewer and with more chunks per split
-        // round (the best cap depends on the rows and the survivors: 32 is
-        // the faster on 1e5 rows of 1250 bits, 64 on 4.7e4 rows of 900).
+        // round: the best cap depends on the rows and the survivors (measured
+        // alone, 32 is the faster on 1e5 rows of 1250 bits and 64 on 4.7e4
+        // rows of 900; inside a plan most segments take 8 to 32).
         if (st == RSR_OK) {
             std::vector<Cand> caps;
-            for (int mc : {32, 128}) {
+            for (int mc : {8, 16, 32, 128}) {
                 rsr::CascadeShape c = s.shape;
                 c.max_chunks = mc;
                 caps.push_back({kCascade, c});
