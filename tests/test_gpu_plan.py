@@ -137,7 +137,8 @@ def test_plan_tuning_cache(rsr_ctx, tmp_path):
     """A tuning-cache file: the first plan times every segment and writes one
     entry per segment; a second plan over the same shapes reads them back
     (no timing: it is created much faster) and gives identical results; a
-    malformed file is rejected with RSR_EINVAL."""
+    malformed file, or an entry with a chunk cap outside 0..1024, is
+    rejected with RSR_EINVAL."""
     import json
     import time
     path = tmp_path / "tune.json"
@@ -176,6 +177,13 @@ def test_plan_tuning_cache(rsr_ctx, tmp_path):
         R.Plan(rsr_ctx, jobs, tune=str(bad))
     assert ei.value.status == R.RSR_EINVAL
     assert bad.read_text() == '{"x": {"choice": 0}}'
+    # A chunk cap outside 0..1024 is a malformed entry too.
+    for chunks in (1025, -1):
+        wrong = {k: dict(e, chunks=chunks) for k, e in entries.items()}
+        bad.write_text(json.dumps(wrong))
+        with pytest.raises(R.RSRError) as ei:
+            R.Plan(rsr_ctx, jobs, tune=str(bad))
+        assert ei.value.status == R.RSR_EINVAL, chunks
 
 
 @pytest.mark.parametrize("choice,tail,first,growth,split,chunks",
